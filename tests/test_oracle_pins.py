@@ -1,0 +1,340 @@
+"""Pins of the exact oracle against things other than itself.
+
+Each test ties the oracle to the definition of the permanent, to a closed
+form, to an independent formula or library, or to a value the paper prints.
+The mutation tests at the end plant plausible mistakes in a copy of the
+oracle (on the CPU) and check that these pins notice them.
+"""
+import itertools
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import inputs as I
+import oracle as O
+from oracle import exact as OX
+
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
+
+
+def gauss_int_matrix(n, seed, lo=-3, hi=3):
+    rng = np.random.default_rng(seed)
+    return (rng.integers(lo, hi + 1, (n, n)) + 1j * rng.integers(lo, hi + 1, (n, n))).astype(np.complex128)
+
+
+def fr(c):
+    return (Fraction(c.real), Fraction(c.imag))
+
+
+def cpow(z, k):
+    re, im = Fraction(1), Fraction(0)
+    for _ in range(k):
+        re, im = re * z[0] - im * z[1], re * z[1] + im * z[0]
+    return re, im
+
+
+# ------------------------------------------------------- definition vs formulas
+
+@pytest.mark.parametrize("n", range(0, 8))
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_four_routes_agree_on_gaussian_integers(n, seed):
+    a = gauss_int_matrix(n, 100 * n + seed)
+    ref = O.perm_exact(a, "brute")
+    assert O.perm_exact(a, "glynn") == ref
+    assert O.perm_exact(a, "ryser") == ref
+    if n > 0:
+        assert O.perm_exact(a, "glynn_direct") == ref
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7])
+def test_definition_on_binary64_unitary_entries(n):
+    a = I.submatrix(I.haar(50, 7), range(n), range(3, 3 + n))
+    assert O.perm_exact(a, "glynn") == O.perm_exact(a, "brute")
+
+
+def test_small_cases_and_empty_matrix():
+    assert O.perm_exact(np.zeros((0, 0), np.complex128)) == (1, 0)
+    assert O.perm_exact(np.array([[2.5 - 1j]])) == (Fraction(5, 2), Fraction(-1))
+    a = np.array([[1, 2], [3, 4]], dtype=np.complex128)
+    assert O.perm_exact(a) == (10, 0)  # 1*4 + 2*3
+
+
+# ---------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("n", range(1, 13))
+def test_all_ones_is_factorial(n):
+    assert O.perm_exact(np.ones((n, n))) == (math.factorial(n), 0)
+
+
+@pytest.mark.parametrize("r", [0.1, 0.2, 10.0, 1 + 1j, 10 + 10j, -0.75 + 0.3j])
+@pytest.mark.parametrize("n", [1, 4, 9])
+def test_all_r_is_r_pow_n_times_factorial(r, n):
+    re, im = cpow(fr(complex(r)), n)
+    f = math.factorial(n)
+    assert O.perm_exact(I.all_r(n, r)) == (re * f, im * f)
+
+
+@pytest.mark.parametrize("n", [1, 3, 8, 11])
+def test_identity_and_permutation_matrices(n):
+    assert O.perm_exact(np.eye(n)) == (1, 0)
+    p = np.random.default_rng(n).permutation(n)
+    assert O.perm_exact(np.eye(n)[p]) == (1, 0)
+
+
+@pytest.mark.parametrize("n", [2, 6, 10])
+def test_diagonal_is_product_of_diagonal(n):
+    rng = np.random.default_rng(n)
+    d = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    a = np.diag(d)
+    re, im = Fraction(1), Fraction(0)
+    for x in d:
+        xr, xi = fr(complex(x))
+        re, im = re * xr - im * xi, re * xi + im * xr
+    assert O.perm_exact(a) == (re, im)
+
+
+def test_rank_one_closed_form():
+    # Per(u v^T) = n! prod u_i prod v_j (every permutation gives the same product)
+    n = 6
+    u = np.array([1, -2, 3, 1, 2, -1], dtype=np.complex128) + 1j * np.array([0, 1, 0, -1, 2, 0])
+    v = np.array([2, 1, -1, 3, 1, 1], dtype=np.complex128)
+    a = np.outer(u, v)
+    pu = np.prod(u)
+    pv = np.prod(v)
+    want = complex(pu * pv) * math.factorial(n)
+    assert O.perm_exact(a) == fr(want)
+
+
+def test_block_diagonal_is_product_of_blocks():
+    a1 = gauss_int_matrix(4, 5)
+    a2 = gauss_int_matrix(3, 6)
+    a = np.zeros((7, 7), np.complex128)
+    a[:4, :4] = a1
+    a[4:, 4:] = a2
+    rng = np.random.default_rng(3)
+    pr, pc = rng.permutation(7), rng.permutation(7)
+    x = O.perm_exact(a1)
+    y = O.perm_exact(a2)
+    want = (x[0] * y[0] - x[1] * y[1], x[0] * y[1] + x[1] * y[0])
+    assert O.perm_exact(a[pr][:, pc]) == want
+
+
+# ------------------------------------------------------------------ invariants
+
+@pytest.mark.parametrize("seed", range(4))
+def test_row_column_permutation_and_transpose_invariance(seed):
+    a = gauss_int_matrix(6, 900 + seed)
+    rng = np.random.default_rng(seed)
+    ref = O.perm_exact(a)
+    assert O.perm_exact(a[rng.permutation(6)]) == ref
+    assert O.perm_exact(a[:, rng.permutation(6)]) == ref
+    assert O.perm_exact(a.T.copy()) == ref
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_multilinear_in_one_row(seed):
+    rng = np.random.default_rng(seed)
+    a = gauss_int_matrix(6, 700 + seed)
+    i = int(rng.integers(6))
+    x = rng.integers(-4, 5, 6) + 1j * rng.integers(-4, 5, 6)
+    y = rng.integers(-4, 5, 6) + 1j * rng.integers(-4, 5, 6)
+    ax, ay, axy = a.copy(), a.copy(), a.copy()
+    ax[i], ay[i], axy[i] = x, y, x + y
+    px, py = O.perm_exact(ax), O.perm_exact(ay)
+    assert O.perm_exact(axy) == (px[0] + py[0], px[1] + py[1])
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_laplace_row_expansion_with_minors(seed):
+    a = gauss_int_matrix(6, 500 + seed)
+    p = O.perm_exact(a)
+    for i in range(6):
+        re = im = Fraction(0)
+        for j in range(6):
+            m = O.minor_perm_exact(a, i, j)
+            ar, ai = fr(complex(a[i, j]))
+            re += ar * m[0] - ai * m[1]
+            im += ar * m[1] + ai * m[0]
+        assert (re, im) == p
+
+
+def test_mpmath_cross_check():
+    mpmath = pytest.importorskip("mpmath")
+    a = I.submatrix(I.haar(64, 3), range(5, 15), range(10))
+    n = 10
+    with mpmath.workdps(60):
+        m = [[mpmath.mpc(complex(a[i, j])) for j in range(n)] for i in range(n)]
+        # Eq. (S1) in mpmath arithmetic: an independent (inexact, 60-digit) route
+        tot = mpmath.mpc(0)
+        for mask in range(1, 1 << n):
+            cols = [j for j in range(n) if (mask >> j) & 1]
+            p = mpmath.mpc(1)
+            for i in range(n):
+                p *= mpmath.fsum(m[i][j] for j in cols)
+            tot += (-1) ** len(cols) * p
+        tot *= (-1) ** n
+        ex = O.perm_exact(a)
+        err = abs(tot - mpmath.mpc(mpmath.mpf(ex[0].numerator) / ex[0].denominator,
+                                   mpmath.mpf(ex[1].numerator) / ex[1].denominator))
+        assert err <= mpmath.mpf(10) ** -45 * abs(tot)
+
+
+def test_gray_range_split_is_exact():
+    g, _ = O.to_gaussian_integers(gauss_int_matrix(9, 11))
+    full = O.glynn_gray_raw(g)
+    total = 1 << 8
+    for pieces in (1, 3, 7, 256):
+        parts = [O.glynn_gray_raw(g, a, b) for a, b in O.split_range(total, pieces)]
+        assert (sum(p[0] for p in parts), sum(p[1] for p in parts)) == full
+    assert O.glynn_raw_parallel(g, 0, total, workers=2) == full
+
+
+# ------------------------------------------------------ values the paper prints
+
+def _printed_match(value: float, printed: str) -> bool:
+    """value rounds to the printed string at the printed precision."""
+    if "E" in printed or "e" in printed:
+        mant = printed.upper().split("E")[0]
+        digits = len(mant.replace("-", "").replace(".", "")) - 1
+        return f"{value:.{digits}E}" == printed.upper() or (float(printed) == 0 and value == 0)
+    decimals = len(printed.split(".")[1]) if "." in printed else 0
+    return f"{value:.{decimals}f}" == printed
+
+
+def _theory_rows():
+    rows = []
+    with open(f"{GOLDEN}/paper_allr_theory.txt") as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            kind, n, r, tre, tim = line.split()
+            rows.append((kind, int(n), complex(r.replace("i", "j")), tre, tim))
+    return rows
+
+
+def test_printed_theory_values_are_r_pow_n_factorial():
+    """Every Per_Theory value of the two BB/FG error tables equals r^n n! at the
+    printed precision (r read as the decimal the table prints)."""
+    rows = _theory_rows()
+    assert len(rows) == 120
+    for kind, n, r, tre, tim in rows:
+        rr = (Fraction(str(r.real)), Fraction(str(r.imag)))
+        re, im = cpow(rr, n)
+        f = math.factorial(n)
+        assert _printed_match(float(re * f), tre), (kind, n, r, tre)
+        assert _printed_match(float(im * f), tim) or (abs(float(im * f)) < 1e-30 and float(tim) == 0), (kind, n, r, tim)
+
+
+@pytest.mark.parametrize("n,r", [(17, 1), (17, 0.1), (17, 10), (17, 0.2), (18, 0.2), (17, 1 + 1j), (18, 1 + 1j),
+                                 (17, 10 + 10j)])
+def test_oracle_reproduces_printed_theory_values(n, r):
+    """The oracle's exact permanent of the all-r matrix (r rounded to binary64)
+    rounds to the value the paper prints."""
+    rows = {(kind, m, rr): (tre, tim) for kind, m, rr, tre, tim in _theory_rows()}
+    kind = "bbfg_complex" if complex(r).imag else "bbfg_real"
+    tre, tim = rows[(kind, n, complex(r))]
+    v = O.perm_exact(I.all_r(n, r))
+    assert _printed_match(float(v[0]), tre)
+    assert _printed_match(float(v[1]), tim) or (float(tim) == 0 and v[1] == 0)
+
+
+def test_worked_example_diag_1_plus_i():
+    """The paper's 45 x 45 diag(1+i) run: (1+i)^45.  The fixture's value is the
+    exact power; the oracle's Glynn walk agrees on diag(1+i) at every n it can
+    afford."""
+    with open(f"{GOLDEN}/paper_worked_examples.txt") as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    name, n, dr, di, pr, pi = rows[0]
+    assert name == "diag_1pi" and int(n) == 45
+    assert cpow((Fraction(int(dr)), Fraction(int(di))), 45) == (int(pr), int(pi))
+    for m in (1, 2, 7, 13):
+        assert O.perm_exact(I.diag_matrix(m, 1 + 1j)) == cpow((Fraction(1), Fraction(1)), m)
+
+
+# ----------------------------------------------------------------- boson layer
+
+def test_completeness_of_output_distribution():
+    """Eq. (1): summed over every output pattern (multisets of n modes out of m),
+    the probabilities add up to 1 for a unitary U.  Pins the t_j! normalisation
+    and the repeated-row gather."""
+    m, n = 6, 4
+    u = I.haar(m, 5)
+    total = Fraction(0)
+    count = 0
+    for t in itertools.combinations_with_replacement(range(m), n):
+        total += O.prob_exact(u, range(n), t)
+        count += 1
+    assert count == math.comb(m + n - 1, n)
+    assert abs(float(total) - 1.0) < 1e-13
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_multiplicity_formula_matches_gather_plus_glynn(seed):
+    rng = np.random.default_rng(seed)
+    m, n = 40, 7
+    u = I.haar(m, 9)
+    modes = rng.choice(m, 4, replace=False)
+    pat = np.sort(np.concatenate([np.repeat(modes[:1], 3), np.repeat(modes[1:2], 2), modes[2:]]))[:n]
+    pat = np.sort(np.concatenate([pat, rng.choice(m, n - len(pat))]))
+    assert len(pat) == n
+    assert O.prob_multiplicity(u, range(n), pat) == O.prob_exact(u, range(n), pat)
+
+
+def test_probability_without_collisions_is_abs_perm_squared():
+    u = I.haar(20, 4)
+    out = [1, 4, 7, 9, 15]
+    p = O.perm_exact(O.gather_u_st(u, range(5), out))
+    assert O.prob_exact(u, range(5), out) == p[0] ** 2 + p[1] ** 2
+
+
+# ----------------------------------------------------- integer exactness check
+
+def test_config1_integer_matrix_is_certified():
+    c = O.certify_int_exact(I.config1_int12())
+    assert c["certified"] and c["max_partial_product"] < 2 ** 53 and c["sum_abs_terms"] < 2 ** 53
+    assert not O.certify_int_exact(I.all_r(12, 100))["certified"]
+
+
+# ------------------------------------------------------------- mutation tests
+
+def _pins_fail(monkeypatch, attr, mutant):
+    """Apply a mutation to the oracle module and report whether the cheap pins
+    above catch it."""
+    monkeypatch.setattr(OX, attr, mutant)
+    failures = 0
+    for n in (3, 5, 6):
+        a = gauss_int_matrix(n, 4242 + n)
+        brute = O.perm_exact(a, "brute")
+        try:
+            if O.perm_exact(a, "glynn") != brute:
+                failures += 1
+            # the same walk cut into pieces, each seeded at its start
+            g, _ = O.to_gaussian_integers(a)
+            parts = [OX.glynn_gray_raw(g, k0, k1) for k0, k1 in O.split_range(1 << (n - 1), 3)]
+            raw = (sum(p[0] for p in parts), sum(p[1] for p in parts))
+            if raw != (brute[0] * (1 << (n - 1)), brute[1] * (1 << (n - 1))):
+                failures += 1
+        except ArithmeticError:
+            failures += 1
+    return failures > 0
+
+
+def test_mutation_not_a_gray_code_is_caught(monkeypatch):
+    # plain binary counting instead of the reflected Gray code
+    assert _pins_fail(monkeypatch, "gray", lambda k: k)
+
+
+def test_mutation_off_by_one_column_is_caught(monkeypatch):
+    assert _pins_fail(monkeypatch, "flipped_column", lambda w0, w1: max(0, (w0 ^ w1).bit_length() - 1))
+
+
+def test_mutation_wrong_fixed_delta_is_caught(monkeypatch):
+    # off by one: bit b drives column b, so delta_0 is no longer fixed to +1
+    assert _pins_fail(monkeypatch, "delta_of_word", lambda w, n: [(-1 if (w >> b) & 1 else 1) for b in range(n)])
+
+
+def test_mutation_transposed_operand_in_complex_product_is_caught(monkeypatch):
+    # (a+ib)(c+id) with the imaginary part's operands swapped wrongly
+    assert _pins_fail(monkeypatch, "_cmul", lambda x, y: (x[0] * y[0] - x[1] * y[1], x[0] * y[0] + x[1] * y[1]))
