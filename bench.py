@@ -1,0 +1,177 @@
+"""Benchmark: Gray-code permanent sweep on one MI355X.
+
+Workload (one "step"): the permanent of the n = 40 complex128 submatrix of
+the Haar-random 1600 x 1600 unitary (seed 31; rows drawn with seed 72, first
+40 columns), BB/FG (Glynn) formula, 2^39 Gray-code terms, compensated
+double-double outer sum -- one call of ph_perm with the input resident in HBM.
+
+Reported: Gray-code terms/s (whole job = one GPU), the sweep's achieved
+algorithmic FP64 rate against the chip's vector-FP64 peak, and the exact CPU
+oracle timed on a bounded sample of the same sweep on the host's cores.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 40] [--extras]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_VECTOR_TFLOPS = 78.6  # 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU
+
+
+def flops_per_term(n: int) -> int:
+    """Algorithmic flops of one Glynn term: 2n (row update, n complex adds)
+    + 6(n-1) (n-1 complex multiplies) + 2 (signed accumulate)."""
+    return 8 * n - 4
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("sweep.hpp", "sweep_single.hip", "dd.hpp"):
+        with open(os.path.join(ROOT, "paper_1606_05836_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(n: int):
+    """HBM bytes per sweep launch measured by rocprofv3 counters, if the
+    committed summary was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"sweep_glynn_n{n}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(a, n: int, seconds: float = 15.0):
+    """Exact oracle (oracle/pool.py) on a contiguous slice of the same Gray
+    sweep, over all host cores; terms/s scaled to the metric's unit."""
+    import oracle
+
+    cores = oracle.host_cores()
+    g, _ = oracle.to_gaussian_integers(a)
+    # calibrate on one core, then size the sample for ~`seconds` on all cores
+    t0 = time.perf_counter()
+    oracle.glynn_gray_raw(g, 0, 256)
+    per_term = (time.perf_counter() - t0) / 256
+    terms = max(cores * 256, int(seconds * cores / per_term))
+    terms = min(terms, 1 << (n - 1))
+    t0 = time.perf_counter()
+    oracle.glynn_raw_parallel(g, 0, terms, workers=cores)
+    dt = time.perf_counter() - t0
+    return {
+        "value": terms / dt,
+        "unit": "Gray-code terms/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"exact Python-integer Glynn walk over Gray indices [0, {terms}) of the same n={n} matrix "
+                  f"({terms} of 2^{n - 1} terms, {dt:.1f} s, contiguous ranges per process)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=40)
+    ap.add_argument("--accum", default="dd")
+    ap.add_argument("--chunk-log2", type=int, default=0)
+    ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs on a single "
+              f"MI355X; multi-GPU sharding of the Gray range is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_1606_05836_amd as ph
+
+    n = args.n
+    a_host = inputs.config3_matrix(n)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    a = torch.from_numpy(a_host).to(dev)
+    out = torch.empty((), dtype=torch.complex128, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    kw = dict(accum=args.accum, chunk_log2=args.chunk_log2, waves=args.waves)
+
+    for _ in range(args.warmup):
+        ph.perm(a, out=out, **kw)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        ph.perm(a, out=out, **kw)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_launch_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    ms = sum(per_launch_ms) / len(per_launch_ms)
+    terms = float(1 << (n - 1))
+    value = terms / (ms / 1e3)
+    achieved = terms * flops_per_term(n) / (ms / 1e3) / 1e12
+    result = complex(out.cpu())
+
+    line = {
+        "metric": f"Gray-code terms/s (n={n} c128)",
+        "value": value,
+        "unit": "terms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"permanent of the n={n} submatrix of Haar(1600, seed 31) (rows seed {32 + n}, first {n} "
+                        f"columns), BB/FG Gray-code sweep, {args.accum} outer sum",
+            "n": n, "terms": int(terms), "algo": "glynn", "accum": args.accum,
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP64_VECTOR_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
+            "traffic": traffic_from_profiles(n),
+        },
+        "per_step_ms": per_launch_ms,
+        "wall_s": wall,
+        "result": [result.real, result.imag],
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(a_host, n)
+    print(json.dumps(line), flush=True)
+    _ = np
+
+
+if __name__ == "__main__":
+    main()

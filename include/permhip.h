@@ -1,0 +1,164 @@
+/* permhip.h -- C ABI of the MI355X (gfx950) permanent library.
+ *
+ * What is computed.  The permanent of an n x n complex matrix,
+ *   Per(A) = sum over permutations s of prod_i a_{i, s(i)},
+ * the quantity whose modulus squared gives the boson-sampling output
+ * probability of the paper's main-text Eq. (1).  Two exact formulas are
+ * offered, both from the Supplementary section "Parallelization and
+ * Optimization":
+ *   PH_GLYNN  Eq. (S2) (BB/FG):  Per(A) = 2^-(n-1) sum_delta (prod_k delta_k)
+ *             prod_i sum_j delta_j a_ij,  delta_0 = +1, delta_k = +-1;
+ *   PH_RYSER  Eq. (S1):          Per(A) = (-1)^n sum_S (-1)^|S| prod_i sum_{j in S} a_ij.
+ * Both are evaluated in Gray-code order (one column changes per term) in
+ * binary64, with the outer sum accumulated either in compensated double-double
+ * (PH_ACC_DD, default) or in plain binary64 (PH_ACC_PLAIN).  The Supplementary
+ * "Analysis of the Precision Issue" explains why Ryser loses accuracy on some
+ * inputs; PH_GLYNN is the default.
+ *
+ * Data layout.  complex128 = two binary64 {re, im}, interleaved (the layout of
+ * C99 double _Complex, std::complex<double> and torch.complex128).  Matrices
+ * are row-major: entry (i, j) of a matrix at A with row stride lda is
+ * A[i * lda + j].
+ *
+ * Memory and streams.  Unless a parameter says "host", pointers are DEVICE
+ * pointers on the current HIP device.  `stream` is a hipStream_t passed as
+ * void* (NULL = the null stream).  Calls enqueue work on the stream and return
+ * without synchronising; results are valid once the stream has reached them.
+ * The caller owns every buffer it passes; the library keeps no reference to
+ * caller memory after a call returns (plans excepted, see below).  The
+ * library owns its workspace (per device and stream, grown on demand with
+ * hipMalloc and kept until the process ends).
+ *
+ * Errors.  Every entry point returns PH_OK (0) or a negative PH_E* code and
+ * never aborts.  Argument errors are detected on the host before anything is
+ * enqueued.  A kernel fault is asynchronous and surfaces at the caller's next
+ * synchronisation.  ph_last_error() describes the last failure of the calling
+ * thread.
+ *
+ * Conventions.  n = 0 gives Per = 1 (empty product); n = 1 gives a_00.
+ * NaN and Inf propagate and are not checked.
+ */
+#ifndef PERMHIP_H
+#define PERMHIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  double re, im;
+} ph_c128;
+
+enum { PH_GLYNN = 0, PH_RYSER = 1 };
+enum { PH_ACC_DD = 0, PH_ACC_PLAIN = 1 };
+
+/* Options; pass NULL for the defaults (Glynn, double-double, tuned sizes).
+ *   algo        PH_GLYNN or PH_RYSER
+ *   accum       PH_ACC_DD or PH_ACC_PLAIN
+ *   chunk_log2  log2 of the Gray-code chunk one lane walks between re-seeds
+ *               of its row sums; 0 = library choice.  Values outside the
+ *               range the kernel supports for n are clamped.
+ *   waves       wavefronts per SIMD to launch (1..8); 0 = library choice
+ *   flags       reserved, must be 0 */
+typedef struct {
+  int32_t algo;
+  int32_t accum;
+  int32_t chunk_log2;
+  int32_t waves;
+  uint32_t flags;
+} ph_opts;
+
+enum {
+  PH_OK = 0,
+  PH_EINVAL = -1,       /* bad pointer, size, stride or option */
+  PH_ERANGE = -2,       /* n above the supported maximum */
+  PH_ENOMEM = -3,       /* device allocation failed */
+  PH_EHIP = -4,         /* HIP runtime error (message in ph_last_error) */
+  PH_EUNSUPPORTED = -5  /* no usable gfx950 device */
+};
+
+#define PH_NMAX 52      /* largest n of ph_perm / batched plans */
+#define PH_NMAX_GRAD 32 /* largest n of ph_perm_grad and the boson layer */
+
+/* Per(A) of one n x n matrix into *out (one complex128, device).
+ * A: device, row stride lda >= n (elements).  0 <= n <= PH_NMAX.
+ * The 2^(n-1) (Glynn) or 2^n (Ryser) terms are cut into contiguous Gray-code
+ * chunks, one per GPU lane at a time; see the formulas above. */
+int ph_perm(const ph_c128* A, int32_t n, int64_t lda, ph_c128* out, const ph_opts* opt, void* stream);
+
+/* Batched permanents in one launch sequence.  Matrix b is n_host[b] x
+ * n_host[b], row-major and contiguous (lda = n), starting at
+ * A_packed + offsets_host[b] (elements); offsets_host = NULL means the
+ * matrices are packed back to back in order.  out[b] receives Per of matrix
+ * b.  Host arrays n_host and offsets_host have `batch` entries.  Convenience
+ * wrapper: create a plan, execute it, destroy it. */
+int ph_perm_batched(const ph_c128* A_packed, const int64_t* offsets_host, const int32_t* n_host, int64_t batch,
+                    ph_c128* out, const ph_opts* opt, void* stream);
+
+/* Plans for repeated batched calls with the same sizes.  ph_plan_create
+ * sorts the matrices by size (largest first), splits each into work items of
+ * 64-chunk groups, allocates the plan's workspace, picks chunk lengths (timing
+ * candidates on `stream` when opt->chunk_log2 == 0 and no tuned value is
+ * cached for this device), and records prep, sweep and finalize kernels in one
+ * hipGraph.  ph_plan_execute replays the graph with the given input and output
+ * (one hipGraphLaunch; the kernel arguments are updated in place when the
+ * pointers differ from the last call).  A plan is bound to the device that
+ * was current at creation and may be used from one thread at a time. */
+int ph_plan_create(const int32_t* n_host, const int64_t* offsets_host, int64_t batch, const ph_opts* opt,
+                   void* stream, void** plan);
+int ph_plan_execute(void* plan, const ph_c128* A_packed, ph_c128* out, void* stream);
+int ph_plan_destroy(void* plan);
+
+/* Gradient of the permanent.  A holds `batch` contiguous n x n matrices
+ * (batch * n * n complex128).  For each matrix the library forms
+ *   M_ij = d Per(A) / d a_ij = Per(A with row i and column j removed)
+ * by differentiating Eq. (S2) term by term inside one Gray-code sweep, and
+ * writes grad_A[b] = g_b * conj(M) elementwise, with g_b = grad_out[b] (the
+ * upstream gradient, PyTorch's conjugate-Wirtinger convention); grad_out =
+ * NULL means g_b = 1, i.e. grad_A = conj(M).  perm_out (nullable) receives
+ * Per(A[b]).  1 <= n <= PH_NMAX_GRAD.  opt->accum selects the accumulation of
+ * the sums over terms; opt->algo must be PH_GLYNN. */
+int ph_perm_grad(const ph_c128* A, int32_t n, int64_t batch, const ph_c128* grad_out, ph_c128* perm_out,
+                 ph_c128* grad_A, const ph_opts* opt, void* stream);
+
+/* Boson-sampling output probabilities, main-text Eq. (1):
+ *   Pr[S -> T_p] = |Per(U_{S,T_p})|^2 / (prod_i s_i! prod_j t_j!),
+ * U: m x m unitary (device, row stride ldu), indexed [output mode, input mode].
+ * in_modes (host, n entries): input mode of each photon (a mode holding s
+ * photons appears s times).  patterns (host, n_patterns x n): output mode of
+ * each photon of pattern p, likewise with repeats.  U_{S,T} has rows =
+ * pattern modes and columns = input modes, both in the given order.
+ * probs (device, n_patterns doubles) receives the probabilities.
+ * 1 <= n <= PH_NMAX_GRAD for the gradient entry point, n <= PH_NMAX here. */
+int ph_boson_probs(const ph_c128* U, int32_t m, int64_t ldu, const int32_t* in_modes, int32_t n,
+                   const int32_t* patterns, int64_t n_patterns, double* probs, const ph_opts* opt, void* stream);
+
+/* Gradient of L = sum_p w_p Pr[S -> T_p] with respect to the columns of U
+ * used by the inputs: dU (device, m x n, row stride lddu) receives
+ * dL/dU[:, in_modes[k]] for k = 0..n-1 (column k of dU belongs to input
+ * photon k; PyTorch's conjugate-Wirtinger convention), accumulated over all
+ * patterns and repeated rows in a fixed order.  weights (device, n_patterns
+ * doubles) or NULL for w_p = 1.  probs (device, nullable) receives the
+ * probabilities as a by-product.  dU is overwritten, not accumulated into. */
+int ph_boson_probs_grad(const ph_c128* U, int32_t m, int64_t ldu, const int32_t* in_modes, int32_t n,
+                        const int32_t* patterns, int64_t n_patterns, const double* weights, double* probs,
+                        ph_c128* dU, int64_t lddu, const ph_opts* opt, void* stream);
+
+/* Achieved FP64 FMA rate of this device (microbenchmark): runs `iters`
+ * dependent-chain-free FMA loops on every CU and returns GFLOP/s in *gflops
+ * (host).  Synchronises the stream. */
+int ph_fp64_peak(int64_t iters, double* gflops, void* stream);
+
+/* Message for the last failure on the calling thread (never NULL). */
+const char* ph_last_error(void);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int ph_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PERMHIP_H */

@@ -1,0 +1,17 @@
+"""MI355X (gfx950) permanents: Gray-code BB/FG (Glynn) and Ryser sweeps in HIP.
+
+The computation lives in libpermhip.so (C ABI: include/permhip.h); this
+package is its Python binding plus a torch.autograd.Function wrapper.
+"""
+from .permhip import (  # noqa: F401
+    PermhipError,
+    Plan,
+    boson_probs,
+    boson_probs_grad,
+    fp64_peak,
+    lib,
+    perm,
+    perm_batched,
+    perm_grad,
+    version,
+)

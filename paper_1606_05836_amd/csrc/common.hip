@@ -1,0 +1,123 @@
+// Table builder (staging of A) and final reduction kernels.
+#include "dd.hpp"
+#include "ph_internal.hpp"
+#include "sweep.hpp"
+
+namespace ph {
+
+// Staging: builds the n-column table the sweep reads (see sweep.hpp):
+//   BB/FG  T[0] = a_{.,0},  T[j] = -2 a_{.,j} (j >= 1)
+//   Ryser  T[j] = a_{.,j}
+// stored column-major (column j is n contiguous complex entries).  Scaling by
+// -2 is exact, so the Gray step r_i += 2 delta_c(new) a_ic of Eq. (S2) is one
+// correctly rounded add per component.
+__device__ __forceinline__ void prep_one(const double2* __restrict__ a, int64_t lda, int n, int algo,
+                                         double2* __restrict__ tab, int e) {
+  const int i = e / n, j = e % n;  // row-major read
+  double2 v = a[(int64_t)i * lda + j];
+  if (algo == ALGO_GLYNN && j >= 1) v = make_double2(-2.0 * v.x, -2.0 * v.y);
+  tab[(size_t)j * n + i] = v;
+}
+
+__global__ void k_prep(const double2* __restrict__ a, int64_t lda, int n, int algo, double2* __restrict__ tab) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n * n) prep_one(a, lda, n, algo, tab, e);
+}
+
+__global__ void k_prep_batched(const MatDesc* __restrict__ mats, int algo) {
+  const MatDesc m = mats[blockIdx.x];
+  for (int e = threadIdx.x; e < m.n * m.n; e += blockDim.x) prep_one(m.a, m.lda, m.n, algo, m.tab, e);
+}
+
+// Fixed-order reduction of partials [begin, end) by one block: thread t sums a
+// contiguous slice in order, then thread 0 sums the slice totals in order.
+// Then the formula's scale: 2^-(n-1) (BB/FG, exact on both halves of the
+// double-double) or (-1)^n (Ryser), and a single rounding to complex128.
+__device__ void finalize_range(const double4* __restrict__ p, int64_t begin, int64_t end, int n, int algo,
+                               int plain, double2* __restrict__ out) {
+  __shared__ dd2 part[256];
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int64_t cnt = end - begin;
+  const int64_t b0 = begin + cnt * t / nt, b1 = begin + cnt * (t + 1) / nt;
+  dd2 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t q = b0; q < b1; ++q) {
+    const double4 v = p[q];
+    if (plain) {
+      acc.hr += v.x;
+      acc.hi += v.z;
+    } else {
+      acc = dd_add(acc, dd2{v.x, v.y, v.z, v.w});
+    }
+  }
+  part[t] = acc;
+  __syncthreads();
+  if (t == 0) {
+    dd2 s = part[0];
+    for (int q = 1; q < nt; ++q) {
+      if (plain) {
+        s.hr += part[q].hr;
+        s.hi += part[q].hi;
+      } else {
+        s = dd_add(s, part[q]);
+      }
+    }
+    double2 r;
+    if (n == 0) {
+      r = make_double2(1.0, 0.0);  // permanent of the empty matrix
+    } else if (algo == ALGO_GLYNN) {
+      r.x = ldexp(s.hr, -(n - 1)) + ldexp(s.lr, -(n - 1));
+      r.y = ldexp(s.hi, -(n - 1)) + ldexp(s.li, -(n - 1));
+    } else {
+      const double sg = (n & 1) ? -1.0 : 1.0;
+      r.x = sg * (s.hr + s.lr);
+      r.y = sg * (s.hi + s.li);
+    }
+    *out = r;
+  }
+}
+
+__global__ void k_finalize_single(const double4* __restrict__ p, int64_t nparts, int n, int algo, int plain,
+                                  double2* __restrict__ out) {
+  finalize_range(p, 0, nparts, n, algo, plain, out);
+}
+
+__global__ void k_finalize_batched(const MatDesc* __restrict__ mats, const double4* __restrict__ p, int algo,
+                                   int plain, double2* __restrict__ out) {
+  const MatDesc m = mats[blockIdx.x];
+  finalize_range(p, m.part_begin, m.part_end, m.n, algo, plain, out + m.out_index);
+}
+
+void launch_prep(const double2* a, int64_t lda, int n, int algo, double2* tab, hipStream_t st) {
+  if (n <= 0) return;
+  const int tot = n * n;
+  hipLaunchKernelGGL(k_prep, dim3((tot + 255) / 256), dim3(256), 0, st, a, lda, n, algo, tab);
+}
+
+void launch_prep_batched(const MatDesc* mats, int nmat, int nmax, int algo, hipStream_t st) {
+  (void)nmax;
+  if (nmat <= 0) return;
+  hipLaunchKernelGGL(k_prep_batched, dim3(nmat), dim3(256), 0, st, mats, algo);
+}
+
+void launch_finalize_single(const double4* partials, int64_t nparts, int n, int algo, int plain, double2* out,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize_single, dim3(1), dim3(256), 0, st, partials, nparts, n, algo, plain, out);
+}
+
+void launch_finalize_batched(const MatDesc* mats, int nmat, const double4* partials, int algo, int plain,
+                             double2* out, hipStream_t st) {
+  if (nmat <= 0) return;
+  hipLaunchKernelGGL(k_finalize_batched, dim3(nmat), dim3(64), 0, st, mats, partials, algo, plain, out);
+}
+
+const void* single_kernel(int n, int algo) {
+  if (n >= 1 && n <= 16) return ph_single_kernel_1_16(n, algo);
+  if (n <= 24) return ph_single_kernel_17_24(n, algo);
+  if (n <= 32) return ph_single_kernel_25_32(n, algo);
+  if (n <= 40) return ph_single_kernel_33_40(n, algo);
+  if (n <= 46) return ph_single_kernel_41_46(n, algo);
+  if (n <= 52) return ph_single_kernel_47_52(n, algo);
+  return nullptr;
+}
+
+}  // namespace ph

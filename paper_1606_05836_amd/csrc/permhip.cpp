@@ -1,0 +1,242 @@
+// Host side of the C ABI declared in include/permhip.h: argument checks,
+// workspace, launch geometry, dispatch to the gfx950 kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "permhip.h"
+#include "ph_host.hpp"
+#include "ph_internal.hpp"
+
+namespace ph {
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string t_err = "no error";
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  t_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(PH_EHIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+// ------------------------------------------------------------------ devices
+
+struct DevInfo {
+  int cus = 0;
+  std::string arch;
+};
+
+static std::mutex g_mu;
+static std::map<int, DevInfo> g_dev;
+
+int device_info(int* dev_out, DevInfo* info) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_dev.find(dev);
+  if (it == g_dev.end()) {
+    hipDeviceProp_t p;
+    e = hipGetDeviceProperties(&p, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    DevInfo d;
+    d.cus = p.multiProcessorCount;
+    d.arch = p.gcnArchName;
+    if (d.arch.rfind("gfx950", 0) != 0)
+      return fail(PH_EUNSUPPORTED, "device %d is %s; this library is built for gfx950", dev, d.arch.c_str());
+    it = g_dev.emplace(dev, d).first;
+  }
+  *dev_out = dev;
+  *info = it->second;
+  return PH_OK;
+}
+
+int num_cus() {
+  int dev;
+  DevInfo d;
+  if (device_info(&dev, &d) != PH_OK) return 0;
+  return d.cus;
+}
+
+// --------------------------------------------------------------- workspace
+
+struct Buf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+static std::map<std::pair<int, hipStream_t>, Buf> g_ws;
+
+// Library-owned scratch for one (device, stream); grown on demand.  Work on
+// one stream is ordered, so reuse across calls on that stream is safe.
+int workspace(hipStream_t st, size_t bytes, void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Buf& b = g_ws[{dev, st}];
+  if (b.cap < bytes) {
+    if (b.p) {
+      // the old buffer may still be in use by queued work on this stream
+      e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+      hipFree(b.p);
+      b.p = nullptr;
+      b.cap = 0;
+    }
+    size_t cap = std::max(bytes, (size_t)1 << 20);
+    e = hipMalloc(&b.p, cap);
+    if (e != hipSuccess) return fail(PH_ENOMEM, "hipMalloc(%zu): %s", cap, hipGetErrorString(e));
+    b.cap = cap;
+  }
+  *out = b.p;
+  return PH_OK;
+}
+
+// ------------------------------------------------------------------ options
+
+int read_opts(const ph_opts* o, Opts* r) {
+  Opts d;
+  if (o) {
+    if (o->algo != PH_GLYNN && o->algo != PH_RYSER) return fail(PH_EINVAL, "opts.algo=%d", o->algo);
+    if (o->accum != PH_ACC_DD && o->accum != PH_ACC_PLAIN) return fail(PH_EINVAL, "opts.accum=%d", o->accum);
+    if (o->chunk_log2 < 0 || o->chunk_log2 > 62) return fail(PH_EINVAL, "opts.chunk_log2=%d", o->chunk_log2);
+    if (o->waves < 0 || o->waves > 8) return fail(PH_EINVAL, "opts.waves=%d", o->waves);
+    if (o->flags != 0) return fail(PH_EINVAL, "opts.flags must be 0");
+    d.algo = o->algo;
+    d.plain = o->accum == PH_ACC_PLAIN;
+    d.chunk_log2 = o->chunk_log2;
+    d.waves = o->waves;
+  }
+  *r = d;
+  return PH_OK;
+}
+
+int gray_bits(int n, int algo) { return algo == PH_GLYNN ? n - 1 : n; }
+
+int min_chunk_log2(int nb) { return nb >= 4 ? 4 : (nb >= 1 ? 1 : 0); }
+
+// Chunk length: long enough to amortise the O(n^2) seed over the O(n) steps,
+// short enough to leave work for every lane and to bound row-sum drift.
+int pick_chunk_log2(int n, int algo, int requested) {
+  const int nb = gray_bits(n, algo);
+  const int lo = min_chunk_log2(nb);
+  int c = requested > 0 ? requested : std::min(12, nb - 13);
+  return std::max(lo, std::min(c, nb));
+}
+
+}  // namespace ph
+
+using namespace ph;
+
+// ======================================================================= ABI
+
+extern "C" const char* ph_last_error(void) { return t_err.c_str(); }
+
+extern "C" int ph_version(void) { return 10000; }
+
+extern "C" int ph_perm(const ph_c128* A, int32_t n, int64_t lda, ph_c128* out, const ph_opts* opt, void* stream) {
+  Opts o;
+  int rc = read_opts(opt, &o);
+  if (rc) return rc;
+  if (n < 0) return fail(PH_EINVAL, "n=%d < 0", n);
+  if (n > PH_NMAX) return fail(PH_ERANGE, "n=%d > %d", n, PH_NMAX);
+  if (!out) return fail(PH_EINVAL, "out is NULL");
+  if (n > 0 && !A) return fail(PH_EINVAL, "A is NULL");
+  if (n > 0 && lda < n) return fail(PH_EINVAL, "lda=%lld < n=%d", (long long)lda, n);
+  int dev;
+  DevInfo di;
+  if ((rc = device_info(&dev, &di))) return rc;
+  return perm_single(reinterpret_cast<const double2*>(A), n, lda, reinterpret_cast<double2*>(out), o,
+                     (hipStream_t)stream, di.cus);
+}
+
+namespace ph {
+
+int perm_single(const double2* A, int n, int64_t lda, double2* out, const Opts& o, hipStream_t st, int cus) {
+  hipError_t e;
+  if (n == 0) {
+    launch_finalize_single(nullptr, 0, 0, o.algo, o.plain, out, st);
+    e = hipGetLastError();
+    return e == hipSuccess ? PH_OK : hip_fail(e, "finalize launch");
+  }
+  const int nb = gray_bits(n, o.algo);
+  const int c = pick_chunk_log2(n, o.algo, o.chunk_log2);
+  const uint64_t nchunks = (uint64_t)1 << (nb - c);
+  const uint64_t nsuper = (nchunks + 63) / 64;
+  const void* kern = single_kernel(n, o.algo);
+  if (!kern) return fail(PH_ERANGE, "no kernel for n=%d", n);
+  const size_t lds = (size_t)n * n * sizeof(double2);
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds);
+  if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+  if (per_cu < 1) return fail(PH_EHIP, "kernel for n=%d cannot be resident", n);
+  if (o.waves > 0) per_cu = std::min(per_cu, o.waves);
+  uint64_t blocks = (uint64_t)cus * per_cu;
+  blocks = std::min<uint64_t>(blocks, (nsuper + 3) / 4);
+  blocks = std::max<uint64_t>(blocks, 1);
+  const uint64_t nwaves = blocks * 4;
+  const size_t tab_bytes = table_elems(n) * sizeof(double2);
+  const size_t part_off = (tab_bytes + 255) & ~(size_t)255;
+  void* ws = nullptr;
+  int rc = workspace(st, part_off + nwaves * sizeof(double4), &ws);
+  if (rc) return rc;
+  double2* tab = reinterpret_cast<double2*>(ws);
+  double4* parts = reinterpret_cast<double4*>(reinterpret_cast<char*>(ws) + part_off);
+  launch_prep(A, lda, n, o.algo, tab, st);
+  int cc = c;
+  uint64_t nch = nchunks;
+  int plain = o.plain ? 1 : 0;
+  void* args[] = {&tab, &cc, &nch, &parts, &plain};
+  e = hipLaunchKernel(kern, dim3((unsigned)blocks), dim3(256), args, lds, st);
+  if (e != hipSuccess) return hip_fail(e, "sweep launch");
+  launch_finalize_single(parts, (int64_t)nwaves, n, o.algo, o.plain, out, st);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return PH_OK;
+}
+
+}  // namespace ph
+
+// ----------------------------------------------------- not yet implemented
+
+#define PH_TODO(name) return fail(PH_EUNSUPPORTED, name " is not implemented in this build")
+
+extern "C" int ph_perm_batched(const ph_c128*, const int64_t*, const int32_t*, int64_t, ph_c128*, const ph_opts*,
+                               void*) {
+  PH_TODO("ph_perm_batched");
+}
+extern "C" int ph_plan_create(const int32_t*, const int64_t*, int64_t, const ph_opts*, void*, void**) {
+  PH_TODO("ph_plan_create");
+}
+extern "C" int ph_plan_execute(void*, const ph_c128*, ph_c128*, void*) { PH_TODO("ph_plan_execute"); }
+extern "C" int ph_plan_destroy(void*) { PH_TODO("ph_plan_destroy"); }
+extern "C" int ph_perm_grad(const ph_c128*, int32_t, int64_t, const ph_c128*, ph_c128*, ph_c128*, const ph_opts*,
+                            void*) {
+  PH_TODO("ph_perm_grad");
+}
+extern "C" int ph_boson_probs(const ph_c128*, int32_t, int64_t, const int32_t*, int32_t, const int32_t*, int64_t,
+                              double*, const ph_opts*, void*) {
+  PH_TODO("ph_boson_probs");
+}
+extern "C" int ph_boson_probs_grad(const ph_c128*, int32_t, int64_t, const int32_t*, int32_t, const int32_t*,
+                                   int64_t, const double*, double*, ph_c128*, int64_t, const ph_opts*, void*) {
+  PH_TODO("ph_boson_probs_grad");
+}
+extern "C" int ph_fp64_peak(int64_t, double*, void*) { PH_TODO("ph_fp64_peak"); }

@@ -1,0 +1,64 @@
+// Single-matrix sweep kernels, one instance per (n, algorithm).
+//
+// This file is compiled once per size range (-DPH_NLO=.. -DPH_NHI=..) so that
+// the instances build in parallel; each compilation exports one lookup
+// function ph_single_kernel_<lo>_<hi>(n, algo) returning the kernel handle.
+//
+// Work split: the C = 2^nb / 2^c chunks are grouped in "super-chunks" of 64
+// consecutive chunks (one per lane of a wavefront).  Wave w of the grid takes
+// the contiguous super-chunk range [S w / W, S (w+1) / W), S = ceil(C / 64),
+// keeps a double-double (or plain) accumulator per lane across all of it, and
+// writes one partial per wave -- the per-process contiguous ranges and final
+// reduce of the parallel listings, mapped to wavefronts.
+#include "sweep.hpp"
+#include "ph_internal.hpp"
+
+#ifndef PH_NLO
+#error "define PH_NLO and PH_NHI"
+#endif
+
+namespace ph {
+
+template <int N, int ALGO>
+__global__ __launch_bounds__(256) void k_sweep_single(const double2* __restrict__ tab, int c, uint64_t nchunks,
+                                                      double4* __restrict__ partials, int plain) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
+  const uint64_t nsuper = (nchunks + 63) >> 6;
+  const uint64_t s0 = nsuper * wave / nwaves;
+  const uint64_t s1 = nsuper * (wave + 1) / nwaves;
+  extern __shared__ double2 lds_tab[];
+  stage_table<N>(lds_tab, tab);
+  Resident<N, ALGO> res;
+  res.load(lds_tab);
+  dd2 acc = {0.0, 0.0, 0.0, 0.0};
+  for (uint64_t s = s0; s < s1; ++s) {
+    const uint64_t chunk = (s << 6) + lane;
+    sweep_chunk<N, ALGO>(chunk << c, c, res, lds_tab, acc, plain != 0, chunk < nchunks);
+  }
+  acc = wave_reduce(acc, plain != 0);
+  if (lane == 0) partials[wave] = make_double4(acc.hr, acc.lr, acc.hi, acc.li);
+}
+
+template <int N>
+static const void* pick(int algo) {
+  return algo == ALGO_GLYNN ? (const void*)&k_sweep_single<N, ALGO_GLYNN>
+                            : (const void*)&k_sweep_single<N, ALGO_RYSER>;
+}
+
+template <int... Is>
+static const void* lookup(int n, int algo, std::integer_sequence<int, Is...>) {
+  const void* out = nullptr;
+  ((n == PH_NLO + Is ? (out = pick<PH_NLO + Is>(algo), 0) : 0), ...);
+  return out;
+}
+
+}  // namespace ph
+
+#define PH_CAT2(a, b, c) a##b##_##c
+#define PH_CAT(a, b, c) PH_CAT2(a, b, c)
+
+const void* PH_CAT(ph_single_kernel_, PH_NLO, PH_NHI)(int n, int algo) {
+  return ph::lookup(n, algo, std::make_integer_sequence<int, PH_NHI - PH_NLO + 1>{});
+}

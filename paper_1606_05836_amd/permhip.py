@@ -1,0 +1,268 @@
+"""ctypes binding of libpermhip.so (the C ABI in include/permhip.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Torch tensors supply device memory and the current stream.  If the
+shared library is missing the calls raise instead of falling back to anything
+else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpermhip.so")
+
+PH_GLYNN, PH_RYSER = 0, 1
+PH_ACC_DD, PH_ACC_PLAIN = 0, 1
+PH_OK, PH_EINVAL, PH_ERANGE, PH_ENOMEM, PH_EHIP, PH_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+PH_NMAX, PH_NMAX_GRAD = 52, 32
+
+EXPORTS = ("ph_perm", "ph_perm_batched", "ph_plan_create", "ph_plan_execute", "ph_plan_destroy",
+           "ph_perm_grad", "ph_boson_probs", "ph_boson_probs_grad", "ph_fp64_peak", "ph_last_error",
+           "ph_version")
+
+
+class PhOpts(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("accum", ctypes.c_int32), ("chunk_log2", ctypes.c_int32),
+                ("waves", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class PermhipError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"permhip error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libpermhip.so once and declare the signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1606_05836_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    op = ctypes.POINTER(PhOpts)
+    P = ctypes.POINTER
+    L.ph_perm.argtypes = [vp, i32, i64, vp, op, vp]
+    L.ph_perm_batched.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int32), i64, vp, op, vp]
+    L.ph_plan_create.argtypes = [P(ctypes.c_int32), P(ctypes.c_int64), i64, op, vp, P(ctypes.c_void_p)]
+    L.ph_plan_execute.argtypes = [vp, vp, vp, vp]
+    L.ph_plan_destroy.argtypes = [vp]
+    L.ph_perm_grad.argtypes = [vp, i32, i64, vp, vp, vp, op, vp]
+    L.ph_boson_probs.argtypes = [vp, i32, i64, P(ctypes.c_int32), i32, P(ctypes.c_int32), i64, dp, op, vp]
+    L.ph_boson_probs_grad.argtypes = [vp, i32, i64, P(ctypes.c_int32), i32, P(ctypes.c_int32), i64, dp, dp, vp,
+                                      i64, op, vp]
+    L.ph_fp64_peak.argtypes = [i64, P(ctypes.c_double), vp]
+    L.ph_last_error.restype = ctypes.c_char_p
+    L.ph_last_error.argtypes = []
+    L.ph_version.restype = ctypes.c_int
+    L.ph_version.argtypes = []
+    for name in EXPORTS:
+        if name not in ("ph_last_error", "ph_version"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(rc: int) -> None:
+    if rc != PH_OK:
+        raise PermhipError(rc, lib().ph_last_error().decode())
+
+
+def opts(algo: str | int = "glynn", accum: str | int = "dd", chunk_log2: int = 0, waves: int = 0) -> PhOpts:
+    a = {"glynn": PH_GLYNN, "ryser": PH_RYSER}.get(algo, algo)
+    c = {"dd": PH_ACC_DD, "plain": PH_ACC_PLAIN}.get(accum, accum)
+    return PhOpts(int(a), int(c), int(chunk_log2), int(waves), 0)
+
+
+def _stream(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr() if t is not None else 0)
+
+
+def _need_c128_cuda(name: str, t: torch.Tensor):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError(f"{name} must be a complex128 CUDA tensor")
+
+
+def perm(a: torch.Tensor, algo="glynn", accum="dd", chunk_log2: int = 0, waves: int = 0,
+         out: torch.Tensor | None = None) -> torch.Tensor:
+    """Per(a) for one n x n complex128 matrix on the GPU (rows may be strided).
+    Returns a 0-dim complex128 tensor on the same device."""
+    _need_c128_cuda("a", a)
+    if a.dim() != 2 or a.shape[0] != a.shape[1]:
+        raise ValueError("a must be n x n")
+    n = a.shape[0]
+    if n > 0 and a.stride(1) != 1:
+        a = a.contiguous()
+    lda = a.stride(0) if n > 0 else 1
+    if out is None:
+        out = torch.empty((), dtype=torch.complex128, device=a.device)
+    o = opts(algo, accum, chunk_log2, waves)
+    check(lib().ph_perm(_ptr(a), n, lda, _ptr(out), ctypes.byref(o), _stream(a)))
+    return out
+
+
+def _pack(mats: Sequence[torch.Tensor]):
+    ns = [int(m.shape[0]) for m in mats]
+    flat = torch.cat([m.reshape(-1) for m in mats]) if mats else None
+    return ns, flat
+
+
+class Plan:
+    """A batched-permanent plan (ph_plan_create / execute / destroy)."""
+
+    def __init__(self, ns: Sequence[int], offsets: Sequence[int] | None = None, algo="glynn", accum="dd",
+                 chunk_log2: int = 0, waves: int = 0, device=None):
+        self.ns = [int(x) for x in ns]
+        self.batch = len(self.ns)
+        self.device = torch.device(device or "cuda")
+        self._n = (ctypes.c_int32 * max(1, self.batch))(*self.ns)
+        self._off = None
+        if offsets is not None:
+            self._off = (ctypes.c_int64 * max(1, self.batch))(*[int(x) for x in offsets])
+        self._opts = opts(algo, accum, chunk_log2, waves)
+        h = ctypes.c_void_p(0)
+        with torch.cuda.device(self.device):
+            st = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+            check(lib().ph_plan_create(self._n, self._off, self.batch, ctypes.byref(self._opts), st,
+                                       ctypes.byref(h)))
+        self._h = h
+
+    def __call__(self, a_packed: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        _need_c128_cuda("a_packed", a_packed)
+        if not a_packed.is_contiguous():
+            raise ValueError("a_packed must be contiguous")
+        if out is None:
+            out = torch.empty(self.batch, dtype=torch.complex128, device=a_packed.device)
+        check(lib().ph_plan_execute(self._h, _ptr(a_packed), _ptr(out), _stream(a_packed)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            check(lib().ph_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def perm_batched(mats: Sequence[torch.Tensor] | torch.Tensor, algo="glynn", accum="dd", chunk_log2: int = 0,
+                 waves: int = 0) -> torch.Tensor:
+    """Permanents of a list of square complex128 CUDA matrices (or a
+    (batch, n, n) tensor) through ph_perm_batched."""
+    if isinstance(mats, torch.Tensor):
+        if mats.dim() != 3 or mats.shape[1] != mats.shape[2]:
+            raise ValueError("expected (batch, n, n)")
+        mats = list(mats)
+    for m in mats:
+        _need_c128_cuda("matrix", m)
+    ns, flat = _pack(mats)
+    batch = len(ns)
+    dev = mats[0].device if batch else torch.device("cuda")
+    out = torch.empty(batch, dtype=torch.complex128, device=dev)
+    if batch == 0:
+        return out
+    n_arr = (ctypes.c_int32 * batch)(*ns)
+    o = opts(algo, accum, chunk_log2, waves)
+    check(lib().ph_perm_batched(_ptr(flat), None, n_arr, batch, _ptr(out), ctypes.byref(o), _stream(flat)))
+    return out
+
+
+def perm_grad(a: torch.Tensor, grad_out: torch.Tensor | None = None, accum="dd", chunk_log2: int = 0,
+              waves: int = 0, want_perm: bool = True):
+    """(perm, grad) for a (batch, n, n) or (n, n) complex128 CUDA tensor:
+    grad[b] = grad_out[b] * conj(dPer/dA[b]) (grad_out None means 1)."""
+    _need_c128_cuda("a", a)
+    single = a.dim() == 2
+    a3 = a.unsqueeze(0) if single else a
+    if a3.dim() != 3 or a3.shape[1] != a3.shape[2]:
+        raise ValueError("expected (batch, n, n) or (n, n)")
+    a3 = a3.contiguous()
+    batch, n = a3.shape[0], a3.shape[1]
+    g = None
+    if grad_out is not None:
+        _need_c128_cuda("grad_out", grad_out)
+        g = grad_out.reshape(batch).contiguous()
+    p = torch.empty(batch, dtype=torch.complex128, device=a.device) if want_perm else None
+    ga = torch.empty_like(a3)
+    o = opts("glynn", accum, chunk_log2, waves)
+    check(lib().ph_perm_grad(_ptr(a3), n, batch, _ptr(g), _ptr(p), _ptr(ga), ctypes.byref(o), _stream(a3)))
+    if single:
+        return (p[0] if p is not None else None), ga[0]
+    return p, ga
+
+
+def _modes(x, name):
+    arr = [int(v) for v in (x.tolist() if hasattr(x, "tolist") else x)]
+    return arr
+
+
+def boson_probs(u: torch.Tensor, in_modes, patterns, algo="glynn", accum="dd") -> torch.Tensor:
+    """Eq. (1) probabilities for each output pattern (rows of `patterns`)."""
+    _need_c128_cuda("u", u)
+    m = u.shape[0]
+    if u.stride(1) != 1:
+        u = u.contiguous()
+    ins = _modes(in_modes, "in_modes")
+    pats = [_modes(p, "pattern") for p in (patterns.tolist() if hasattr(patterns, "tolist") else patterns)]
+    n = len(ins)
+    npat = len(pats)
+    flat = [v for p in pats for v in p]
+    if any(len(p) != n for p in pats):
+        raise ValueError("every pattern needs n entries")
+    probs = torch.empty(npat, dtype=torch.float64, device=u.device)
+    o = opts(algo, accum)
+    check(lib().ph_boson_probs(_ptr(u), m, u.stride(0), (ctypes.c_int32 * max(1, n))(*ins), n,
+                               (ctypes.c_int32 * max(1, len(flat)))(*flat), npat, _ptr(probs), ctypes.byref(o),
+                               _stream(u)))
+    return probs
+
+
+def boson_probs_grad(u: torch.Tensor, in_modes, patterns, weights: torch.Tensor | None = None, accum="dd"):
+    """(probs, dU) with dU[:, k] = dL/dU[:, in_modes[k]], L = sum_p w_p Pr_p."""
+    _need_c128_cuda("u", u)
+    m = u.shape[0]
+    if u.stride(1) != 1:
+        u = u.contiguous()
+    ins = _modes(in_modes, "in_modes")
+    pats = [_modes(p, "pattern") for p in (patterns.tolist() if hasattr(patterns, "tolist") else patterns)]
+    n, npat = len(ins), len(pats)
+    flat = [v for p in pats for v in p]
+    probs = torch.empty(npat, dtype=torch.float64, device=u.device)
+    du = torch.empty((m, n), dtype=torch.complex128, device=u.device)
+    w = None
+    if weights is not None:
+        w = weights.to(device=u.device, dtype=torch.float64).contiguous()
+    o = opts("glynn", accum)
+    check(lib().ph_boson_probs_grad(_ptr(u), m, u.stride(0), (ctypes.c_int32 * max(1, n))(*ins), n,
+                                    (ctypes.c_int32 * max(1, len(flat)))(*flat), npat, _ptr(w), _ptr(probs),
+                                    _ptr(du), du.stride(0), ctypes.byref(o), _stream(u)))
+    return probs, du
+
+
+def fp64_peak(iters: int = 1 << 16, device=None) -> float:
+    """Achieved FP64 FMA GFLOP/s of the device (microbenchmark kernel)."""
+    g = ctypes.c_double(0.0)
+    dev = torch.device(device or "cuda")
+    st = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    check(lib().ph_fp64_peak(int(iters), ctypes.byref(g), st))
+    return g.value
+
+
+def version() -> int:
+    return lib().ph_version()

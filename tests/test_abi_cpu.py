@@ -1,0 +1,81 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "permhip.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1606_05836_amd import permhip as P
+
+    if not os.path.exists(P.LIB_PATH):
+        from paper_1606_05836_amd.build import build
+
+        build()
+    return P.lib()
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(ph_\w+)\s*\(", txt, re.M)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for want in ("ph_perm", "ph_perm_batched", "ph_plan_create", "ph_plan_execute", "ph_plan_destroy",
+                 "ph_perm_grad", "ph_boson_probs", "ph_boson_probs_grad", "ph_last_error", "ph_version"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_binding_lists_match_header():
+    from paper_1606_05836_amd import permhip as P
+
+    assert sorted(P.EXPORTS) == declared_functions()
+
+
+def test_version(L):
+    assert L.ph_version() >= 10000
+
+
+def _perm(L, a, n, lda, out, o=None):
+    from paper_1606_05836_amd import permhip as P
+
+    return L.ph_perm(ctypes.c_void_p(a), n, lda, ctypes.c_void_p(out), ctypes.byref(o) if o else None, None)
+
+
+def test_argument_errors_are_reported_before_any_device_work(L):
+    from paper_1606_05836_amd import permhip as P
+
+    fake = 0x1000  # never dereferenced: validation fails first
+    assert _perm(L, fake, -1, 1, fake) == P.PH_EINVAL
+    assert b"n=-1" in L.ph_last_error()
+    assert _perm(L, fake, P.PH_NMAX + 1, 64, fake) == P.PH_ERANGE
+    assert _perm(L, fake, 10, 9, fake) == P.PH_EINVAL
+    assert _perm(L, fake, 10, 10, 0) == P.PH_EINVAL
+    assert _perm(L, 0, 10, 10, fake) == P.PH_EINVAL
+    assert _perm(L, fake, 10, 10, fake, P.PhOpts(7, 0, 0, 0, 0)) == P.PH_EINVAL
+    assert _perm(L, fake, 10, 10, fake, P.PhOpts(0, 5, 0, 0, 0)) == P.PH_EINVAL
+    assert _perm(L, fake, 10, 10, fake, P.PhOpts(0, 0, 0, 9, 0)) == P.PH_EINVAL
+    assert _perm(L, fake, 10, 10, fake, P.PhOpts(0, 0, 0, 0, 1)) == P.PH_EINVAL
+
+
+def test_python_binding_rejects_non_device_tensors():
+    import torch
+
+    import paper_1606_05836_amd as ph
+
+    with pytest.raises(TypeError):
+        ph.perm(torch.zeros((3, 3), dtype=torch.complex128))
+    with pytest.raises(TypeError):
+        ph.perm(torch.zeros((3, 3), dtype=torch.float64))
