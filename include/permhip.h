@@ -93,7 +93,11 @@ int ph_perm(const ph_c128* A, int32_t n, int64_t lda, ph_c128* out, const ph_opt
  * A_packed + offsets_host[b] (elements); offsets_host = NULL means the
  * matrices are packed back to back in order.  out[b] receives Per of matrix
  * b.  Host arrays n_host and offsets_host have `batch` entries.  Convenience
- * wrapper: create a plan, execute it, destroy it. */
+ * wrapper around the plans below: the library keeps the plans of the last
+ * few (device, stream, options, sizes) combinations, so a repeated call costs
+ * one graph launch; the first call for a new combination plans (and may time
+ * chunk-length candidates) before it returns.  A plan evicted from this cache
+ * is freed after its stream has finished with it. */
 int ph_perm_batched(const ph_c128* A_packed, const int64_t* offsets_host, const int32_t* n_host, int64_t batch,
                     ph_c128* out, const ph_opts* opt, void* stream);
 
@@ -146,10 +150,13 @@ int ph_boson_probs_grad(const ph_c128* U, int32_t m, int64_t ldu, const int32_t*
                         const int32_t* patterns, int64_t n_patterns, const double* weights, double* probs,
                         ph_c128* dU, int64_t lddu, const ph_opts* opt, void* stream);
 
-/* Achieved FP64 FMA rate of this device (microbenchmark): runs `iters`
- * dependent-chain-free FMA loops on every CU and returns GFLOP/s in *gflops
- * (host).  Synchronises the stream. */
-int ph_fp64_peak(int64_t iters, double* gflops, void* stream);
+/* Achieved FP64 FMA rate of this device (microbenchmark, the FMA-only
+ * reference program of the paper's Supplementary efficiency section): every
+ * lane of 8 wavefronts per SIMD runs 8 independent FMA chains for 32 * iters
+ * FMAs.  *gflops (host) receives the rate; *sclk_mhz (host, nullable) the
+ * shader clock sustained during the run, from the cycle and constant-rate
+ * counters of one wavefront.  Synchronises the stream. */
+int ph_fp64_peak(int64_t iters, double* gflops, double* sclk_mhz, void* stream);
 
 /* Message for the last failure on the calling thread (never NULL). */
 const char* ph_last_error(void);

@@ -36,16 +36,19 @@ FLAGS = [
 ]
 
 DPP_NMAX = 44  # keep equal to DPP_NMAX in csrc/sweep.hpp
-RANGES = [(1, 16), (17, 24), (25, 32), (33, 40), (41, 46), (47, 52)]
+BATCHED_DPP_NMAX = 40  # keep equal to BATCHED_DPP_NMAX in csrc/sweep_batched.hip
+RANGES = [(1, 16), (17, 24), (25, 32), (33, 40), (41, 44), (45, 52)]
+RANGED = ("sweep_single.hip", "sweep_batched.hip")  # compiled once per size range
 
 
 def units():
     """(output object, source, extra flags)"""
     u = []
     for lo, hi in RANGES:
-        u.append((f"sweep_single_{lo}_{hi}.o", "sweep_single.hip", [f"-DPH_NLO={lo}", f"-DPH_NHI={hi}"]))
+        for src in RANGED:
+            u.append((f"{src[:-4]}_{lo}_{hi}.o", src, [f"-DPH_NLO={lo}", f"-DPH_NHI={hi}"]))
     for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".cpp")) and name != "sweep_single.hip":
+        if name.endswith((".hip", ".cpp")) and name not in RANGED:
             u.append((os.path.splitext(name)[0] + ".o", name, []))
     return u
 
@@ -92,8 +95,15 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
         for k in sorted(report):
             f.write(k + " " + " ".join(f"{a}={b}" for a, b in sorted(report[k].items())) + "\n")
     def _n_of(kernel):
-        m = re.search(r"sweep_\w*?ILi(\d+)E", kernel)
-        return int(m.group(1)) if m else 0
+        m = re.search(r"sweep_\w*?ILi(\d+)E(Li(\d+)E)?", kernel)
+        if not m:
+            return 0
+        # batched kernels are templated on the bucket bounds: take the lower
+        # one, DPP is used there up to BATCHED_DPP_NMAX
+        if "batched" in kernel:
+            lo, hi = int(m.group(1)), int(m.group(3) or m.group(1))
+            return hi if lo <= BATCHED_DPP_NMAX else DPP_NMAX + 1
+        return int(m.group(1))
 
     # kernels up to DPP_NMAX (sweep.hpp) read resident columns with DPP: no
     # spill code of any kind (AGPR copies included) is allowed there

@@ -24,9 +24,14 @@ __global__ void k_prep(const double2* __restrict__ a, int64_t lda, int n, int al
   if (e < n * n) prep_one(a, lda, n, algo, tab, e);
 }
 
-__global__ void k_prep_batched(const MatDesc* __restrict__ mats, int algo) {
+__global__ void k_prep_batched(const MatDesc* __restrict__ mats, const double2* __restrict__ a_base, int algo) {
   const MatDesc m = mats[blockIdx.x];
-  for (int e = threadIdx.x; e < m.n * m.n; e += blockDim.x) prep_one(m.a, m.lda, m.n, algo, m.tab, e);
+  for (int e = threadIdx.x; e < m.n * m.n; e += blockDim.x) prep_one(a_base + m.a_off, m.lda, m.n, algo, m.tab, e);
+}
+
+__global__ void k_reset(uint32_t* __restrict__ counters, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) counters[i] = 0;
 }
 
 // Fixed-order reduction of partials [begin, end) by one block: thread t sums a
@@ -93,21 +98,39 @@ void launch_prep(const double2* a, int64_t lda, int n, int algo, double2* tab, h
   hipLaunchKernelGGL(k_prep, dim3((tot + 255) / 256), dim3(256), 0, st, a, lda, n, algo, tab);
 }
 
-void launch_prep_batched(const MatDesc* mats, int nmat, int nmax, int algo, hipStream_t st) {
-  (void)nmax;
-  if (nmat <= 0) return;
-  hipLaunchKernelGGL(k_prep_batched, dim3(nmat), dim3(256), 0, st, mats, algo);
-}
-
 void launch_finalize_single(const double4* partials, int64_t nparts, int n, int algo, int plain, double2* out,
                             hipStream_t st) {
   hipLaunchKernelGGL(k_finalize_single, dim3(1), dim3(256), 0, st, partials, nparts, n, algo, plain, out);
 }
 
-void launch_finalize_batched(const MatDesc* mats, int nmat, const double4* partials, int algo, int plain,
-                             double2* out, hipStream_t st) {
-  if (nmat <= 0) return;
-  hipLaunchKernelGGL(k_finalize_batched, dim3(nmat), dim3(64), 0, st, mats, partials, algo, plain, out);
+// Deterministic bounded values for timing runs (no meaning beyond that).
+__global__ void k_fill_synthetic(double2* a, int64_t count) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < count) {
+    const uint64_t h = (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+    a[i] = make_double2((double)((h >> 11) & 1023) / 2048.0 - 0.25, (double)((h >> 31) & 1023) / 2048.0 - 0.25);
+  }
+}
+
+void launch_fill_synthetic(double2* a, int64_t count, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_fill_synthetic, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, a, count);
+}
+
+const void* prep_batched_kernel() { return (const void*)&k_prep_batched; }
+const void* finalize_batched_kernel() { return (const void*)&k_finalize_batched; }
+const void* reset_kernel() { return (const void*)&k_reset; }
+
+const void* batched_kernel(int bucket, int algo) {
+  switch (bucket) {
+    case 0: return ph_batched_kernel_1_16(algo);
+    case 1: return ph_batched_kernel_17_24(algo);
+    case 2: return ph_batched_kernel_25_32(algo);
+    case 3: return ph_batched_kernel_33_40(algo);
+    case 4: return ph_batched_kernel_41_44(algo);
+    case 5: return ph_batched_kernel_45_52(algo);
+  }
+  return nullptr;
 }
 
 const void* single_kernel(int n, int algo) {
@@ -115,8 +138,8 @@ const void* single_kernel(int n, int algo) {
   if (n <= 24) return ph_single_kernel_17_24(n, algo);
   if (n <= 32) return ph_single_kernel_25_32(n, algo);
   if (n <= 40) return ph_single_kernel_33_40(n, algo);
-  if (n <= 46) return ph_single_kernel_41_46(n, algo);
-  if (n <= 52) return ph_single_kernel_47_52(n, algo);
+  if (n <= 44) return ph_single_kernel_41_44(n, algo);
+  if (n <= 52) return ph_single_kernel_45_52(n, algo);
   return nullptr;
 }
 

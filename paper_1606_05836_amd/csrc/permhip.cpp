@@ -218,15 +218,6 @@ int perm_single(const double2* A, int n, int64_t lda, double2* out, const Opts& 
 
 #define PH_TODO(name) return fail(PH_EUNSUPPORTED, name " is not implemented in this build")
 
-extern "C" int ph_perm_batched(const ph_c128*, const int64_t*, const int32_t*, int64_t, ph_c128*, const ph_opts*,
-                               void*) {
-  PH_TODO("ph_perm_batched");
-}
-extern "C" int ph_plan_create(const int32_t*, const int64_t*, int64_t, const ph_opts*, void*, void**) {
-  PH_TODO("ph_plan_create");
-}
-extern "C" int ph_plan_execute(void*, const ph_c128*, ph_c128*, void*) { PH_TODO("ph_plan_execute"); }
-extern "C" int ph_plan_destroy(void*) { PH_TODO("ph_plan_destroy"); }
 extern "C" int ph_perm_grad(const ph_c128*, int32_t, int64_t, const ph_c128*, ph_c128*, ph_c128*, const ph_opts*,
                             void*) {
   PH_TODO("ph_perm_grad");
@@ -239,4 +230,3 @@ extern "C" int ph_boson_probs_grad(const ph_c128*, int32_t, int64_t, const int32
                                    int64_t, const double*, double*, ph_c128*, int64_t, const ph_opts*, void*) {
   PH_TODO("ph_boson_probs_grad");
 }
-extern "C" int ph_fp64_peak(int64_t, double*, void*) { PH_TODO("ph_fp64_peak"); }

@@ -13,8 +13,8 @@ inline size_t table_elems(int n) { return (size_t)n * n; }
 
 // Per-matrix descriptor used by the batched kernels (device memory).
 struct MatDesc {
-  const double2* a;    // input, row-major
-  int64_t lda;         // row stride of a (elements)
+  int64_t a_off;       // offset of the input (row-major, contiguous) in the packed batch
+  int64_t lda;         // row stride of the input (elements)
   double2* tab;        // table (table_elems(n) complex entries)
   int32_t n;           // order
   int32_t c;           // log2 chunk length
@@ -33,18 +33,24 @@ struct WorkItem {
 
 // size-range kernel lookups (sweep_single.hip compiled once per range)
 const void* single_kernel(int n, int algo);
-// batched persistent kernels (sweep_batched.hip), by size bucket
+// batched persistent kernels (sweep_batched.hip), one per size bucket
+constexpr int NBUCKETS = 6;
+constexpr int BUCKET_LO[NBUCKETS] = {1, 17, 25, 33, 41, 45};
+constexpr int BUCKET_HI[NBUCKETS] = {16, 24, 32, 40, 44, 52};
+inline int bucket_of(int n) {
+  for (int b = 0; b < NBUCKETS; ++b)
+    if (n >= BUCKET_LO[b] && n <= BUCKET_HI[b]) return b;
+  return -1;
+}
 const void* batched_kernel(int bucket, int algo);
-int batched_bucket(int n);       // bucket index of an order n
-int batched_bucket_count();
-int batched_bucket_nmax(int bucket);
 
 void launch_prep(const double2* a, int64_t lda, int n, int algo, double2* tab, hipStream_t st);
-void launch_prep_batched(const MatDesc* mats, int nmat, int nmax, int algo, hipStream_t st);
+const void* prep_batched_kernel();      // k_prep_batched(mats, a_base, algo)
+const void* finalize_batched_kernel();  // k_finalize_batched(mats, partials, algo, plain, out)
+const void* reset_kernel();             // k_reset(counters, count)
+void launch_fill_synthetic(double2* a, int64_t count, hipStream_t st);
 void launch_finalize_single(const double4* partials, int64_t nparts, int n, int algo, int plain, double2* out,
                             hipStream_t st);
-void launch_finalize_batched(const MatDesc* mats, int nmat, const double4* partials, int algo, int plain,
-                             double2* out, hipStream_t st);
 
 }  // namespace ph
 
@@ -53,6 +59,14 @@ PH_DECLARE_RANGE(1, 16)
 PH_DECLARE_RANGE(17, 24)
 PH_DECLARE_RANGE(25, 32)
 PH_DECLARE_RANGE(33, 40)
-PH_DECLARE_RANGE(41, 46)
-PH_DECLARE_RANGE(47, 52)
+PH_DECLARE_RANGE(41, 44)
+PH_DECLARE_RANGE(45, 52)
 #undef PH_DECLARE_RANGE
+#define PH_DECLARE_BUCKET(lo, hi) const void* ph_batched_kernel_##lo##_##hi(int algo);
+PH_DECLARE_BUCKET(1, 16)
+PH_DECLARE_BUCKET(17, 24)
+PH_DECLARE_BUCKET(25, 32)
+PH_DECLARE_BUCKET(33, 40)
+PH_DECLARE_BUCKET(41, 44)
+PH_DECLARE_BUCKET(45, 52)
+#undef PH_DECLARE_BUCKET

@@ -1,0 +1,609 @@
+// Batched permanents: plan construction (size sort, work items, workspace,
+// chunk-length tuning) and one hipGraph per plan holding the reset, prep,
+// per-bucket sweep and finalize kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "permhip.h"
+#include "ph_host.hpp"
+#include "ph_internal.hpp"
+
+namespace ph {
+
+// ----------------------------------------------------------- the plan object
+
+struct KernelNode {
+  hipGraphNode_t node = nullptr;
+  hipKernelNodeParams params{};
+  std::vector<void*> argv;  // pointers into `store`
+  std::vector<char> store;  // argument values
+};
+
+struct PlanImpl {
+  int dev = 0;
+  int algo = 0;
+  bool plain = false;
+  int64_t batch = 0;
+  std::vector<int32_t> n;
+  std::vector<int64_t> off;   // element offsets of the matrices in A_packed
+  std::vector<int32_t> c;     // chunk log2 per matrix (original order)
+  int64_t n_items = 0;
+  char* dmem = nullptr;
+  MatDesc* d_mats = nullptr;
+  WorkItem* d_items = nullptr;
+  uint32_t* d_counters = nullptr;
+  double4* d_parts = nullptr;
+  double2* d_tabs = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<KernelNode> nodes;  // reset, prep, buckets..., finalize
+  int prep_idx = -1, fin_idx = -1;
+  const void* last_a = nullptr;
+  void* last_out = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool launched = false;
+};
+
+template <typename T>
+static void push_arg(KernelNode& k, const T& v) {
+  const size_t at = k.store.size();
+  k.store.resize(at + sizeof(T));
+  std::memcpy(k.store.data() + at, &v, sizeof(T));
+}
+
+static void seal_args(KernelNode& k, const std::vector<size_t>& sizes) {
+  k.argv.clear();
+  size_t at = 0;
+  for (size_t s : sizes) {
+    k.argv.push_back(k.store.data() + at);
+    at += s;
+  }
+  k.params.kernelParams = k.argv.data();
+  k.params.extra = nullptr;
+}
+
+static void destroy_impl(PlanImpl* p) {
+  if (!p) return;
+  if (p->launched) hipStreamSynchronize(p->last_stream);
+  if (p->exec) hipGraphExecDestroy(p->exec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->dmem) hipFree(p->dmem);
+  delete p;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ------------------------------------------------------------- chunk tuning
+
+struct TuneKey {
+  std::string arch;
+  int cus, n, algo, plain;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(arch, cus, n, algo, plain) < std::tie(o.arch, o.cus, o.n, o.algo, o.plain);
+  }
+};
+
+static std::mutex g_tune_mu;
+static std::map<TuneKey, int> g_tune;
+static bool g_tune_loaded = false;
+
+// Range of chunk lengths a plan may use for order n.  The upper bound is the
+// drift budget: row sums are re-seeded every 2^c steps, and c <= 14 keeps the
+// accumulated rounding of the incremental updates far below the 1e-10
+// relative-error target (measured: one 2^19-step chunk at n = 20 still stays
+// under 2e-12).  A batch also wants >= 4 super-chunks per matrix so that all
+// four wavefronts of a workgroup have work.
+static void chunk_range(int n, int algo, int* lo, int* hi) {
+  const int nb = gray_bits(n, algo);
+  const int cmin = min_chunk_log2(nb);
+  int h = std::min(14, nb - 8);
+  h = std::max(h, cmin);
+  h = std::min(h, nb);
+  int l = std::max(cmin, std::min(h, 6));
+  *lo = l;
+  *hi = h;
+}
+
+static int default_chunk(int n, int algo) {
+  int lo, hi;
+  chunk_range(n, algo, &lo, &hi);
+  return std::max(lo, std::min(hi, 12));
+}
+
+static std::string cache_path() {
+  const char* p = getenv("PERMHIP_TUNE_CACHE");
+  return p ? std::string(p) : std::string();
+}
+
+static void load_cache_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const std::string path = cache_path();
+  if (path.empty()) return;
+  std::ifstream f(path);
+  std::string line;
+  // one entry per line: arch cus n algo plain c
+  while (std::getline(f, line)) {
+    std::istringstream is(line);
+    TuneKey k;
+    int c;
+    if (is >> k.arch >> k.cus >> k.n >> k.algo >> k.plain >> c) g_tune[k] = c;
+  }
+}
+
+static void save_cache_locked() {
+  const std::string path = cache_path();
+  if (path.empty()) return;
+  std::ofstream f(path, std::ios::trunc);
+  for (auto& kv : g_tune)
+    f << kv.first.arch << ' ' << kv.first.cus << ' ' << kv.first.n << ' ' << kv.first.algo << ' ' << kv.first.plain
+      << ' ' << kv.second << '\n';
+}
+
+int plan_build(const int32_t* n_host, const int64_t* off_host, int64_t batch, const Opts& o, const int32_t* c_force,
+               hipStream_t st, PlanImpl** out);
+int plan_exec(PlanImpl* p, const double2* a, double2* out, hipStream_t st);
+
+// Time the batched sweep for each candidate chunk length on a synthetic batch
+// of order-n matrices (about 2^27 terms) and keep the fastest.
+static int tune_chunk(int n, int algo, bool plain, hipStream_t st, int* c_out) {
+  int lo, hi;
+  chunk_range(n, algo, &lo, &hi);
+  if (lo == hi) {
+    *c_out = lo;
+    return PH_OK;
+  }
+  const int nb = gray_bits(n, algo);
+  const int64_t copies = nb >= 27 ? 1 : ((int64_t)1 << std::min(27 - nb, 14));
+  const int64_t elems = copies * n * n;
+  double2* a = nullptr;
+  double2* out = nullptr;
+  hipError_t e = hipMalloc(&a, elems * sizeof(double2) + copies * sizeof(double2) + 256);
+  if (e != hipSuccess) return fail(PH_ENOMEM, "tuning buffer: %s", hipGetErrorString(e));
+  out = a + elems;
+  launch_fill_synthetic(a, elems, st);
+  std::vector<int32_t> ns(copies, n), cs(copies);
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  Opts o;
+  o.algo = algo;
+  o.plain = plain;
+  float best = 1e30f;
+  int best_c = default_chunk(n, algo);
+  int rc = PH_OK;
+  for (int c = lo; c <= hi && rc == PH_OK; ++c) {
+    std::fill(cs.begin(), cs.end(), c);
+    PlanImpl* p = nullptr;
+    rc = plan_build(ns.data(), nullptr, copies, o, cs.data(), st, &p);
+    if (rc) break;
+    float ms = 1e30f;
+    for (int rep = 0; rep < 2 && rc == PH_OK; ++rep) {
+      hipEventRecord(e0, st);
+      rc = plan_exec(p, a, out, st);
+      hipEventRecord(e1, st);
+      hipEventSynchronize(e1);
+      float t = 0;
+      hipEventElapsedTime(&t, e0, e1);
+      if (rep == 1) ms = t;
+    }
+    destroy_impl(p);
+    if (ms < best) {
+      best = ms;
+      best_c = c;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipStreamSynchronize(st);
+  hipFree(a);
+  *c_out = best_c;
+  return rc;
+}
+
+int tuned_chunk(int n, int algo, bool plain, hipStream_t st, int* c_out) {
+  int dev = 0;
+  hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  TuneKey k{prop.gcnArchName, prop.multiProcessorCount, n, algo, plain ? 1 : 0};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_cache_locked();
+    auto it = g_tune.find(k);
+    if (it != g_tune.end()) {
+      *c_out = it->second;
+      return PH_OK;
+    }
+  }
+  int c = 0;
+  int rc = tune_chunk(n, algo, plain, st, &c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[k] = c;
+  save_cache_locked();
+  *c_out = c;
+  return PH_OK;
+}
+
+// ------------------------------------------------------------- plan building
+
+// Record reset -> prep -> sweep buckets (largest first) -> finalize as one
+// graph and instantiate it.
+static hipError_t build_graph(PlanImpl* p, const Opts& o, const std::vector<std::pair<int64_t, int64_t>>& bucket_items) {
+  hipError_t e = hipGraphCreate(&p->graph, 0);
+  if (e != hipSuccess) return e;
+  const int cus = num_cus();
+  const int64_t batch = p->batch;
+  hipGraphNode_t prev = nullptr;
+  p->nodes.clear();
+  p->nodes.reserve(NBUCKETS + 3);
+  auto add = [&](KernelNode&& kn) -> hipError_t {
+    p->nodes.push_back(std::move(kn));
+    KernelNode& k = p->nodes.back();
+    k.params.kernelParams = k.argv.data();
+    hipError_t r = hipGraphAddKernelNode(&k.node, p->graph, prev ? &prev : nullptr, prev ? 1 : 0, &k.params);
+    if (r == hipSuccess) prev = k.node;
+    return r;
+  };
+  {
+    KernelNode k;
+    uint32_t* cnt = p->d_counters;
+    int count = NBUCKETS;
+    push_arg(k, cnt);
+    push_arg(k, count);
+    seal_args(k, {sizeof(cnt), sizeof(count)});
+    k.params.func = const_cast<void*>(reset_kernel());
+    k.params.gridDim = dim3(1);
+    k.params.blockDim = dim3(64);
+    k.params.sharedMemBytes = 0;
+    if ((e = add(std::move(k))) != hipSuccess) return e;
+  }
+  if (batch > 0) {
+    KernelNode k;
+    MatDesc* dm = p->d_mats;
+    const double2* a = nullptr;
+    int algo = o.algo;
+    push_arg(k, dm);
+    push_arg(k, a);
+    push_arg(k, algo);
+    seal_args(k, {sizeof(dm), sizeof(a), sizeof(algo)});
+    k.params.func = const_cast<void*>(prep_batched_kernel());
+    k.params.gridDim = dim3((unsigned)batch);
+    k.params.blockDim = dim3(256);
+    k.params.sharedMemBytes = 0;
+    if ((e = add(std::move(k))) != hipSuccess) return e;
+    p->prep_idx = (int)p->nodes.size() - 1;
+  }
+  for (int bk = NBUCKETS - 1; bk >= 0; --bk) {
+    if (bucket_items[bk].first < 0) continue;
+    KernelNode k;
+    const void* kern = batched_kernel(bk, o.algo);
+    const size_t lds = (size_t)BUCKET_HI[bk] * BUCKET_HI[bk] * sizeof(double2);
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds);
+    if (e != hipSuccess) return e;
+    per_cu = std::max(per_cu, 1);
+    if (o.waves > 0) per_cu = std::min(per_cu, o.waves);
+    const int64_t nit = bucket_items[bk].second - bucket_items[bk].first;
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * per_cu, nit));
+    MatDesc* dm = p->d_mats;
+    WorkItem* di = p->d_items;
+    int64_t ib = bucket_items[bk].first, ie = bucket_items[bk].second;
+    uint32_t* cnt = p->d_counters + bk;
+    double4* parts = p->d_parts;
+    int plain = o.plain ? 1 : 0;
+    push_arg(k, dm);
+    push_arg(k, di);
+    push_arg(k, ib);
+    push_arg(k, ie);
+    push_arg(k, cnt);
+    push_arg(k, parts);
+    push_arg(k, plain);
+    seal_args(k, {sizeof(dm), sizeof(di), sizeof(ib), sizeof(ie), sizeof(cnt), sizeof(parts), sizeof(plain)});
+    k.params.func = const_cast<void*>(kern);
+    k.params.gridDim = dim3((unsigned)grid);
+    k.params.blockDim = dim3(256);
+    k.params.sharedMemBytes = (unsigned)lds;
+    if ((e = add(std::move(k))) != hipSuccess) return e;
+  }
+  if (batch > 0) {
+    KernelNode k;
+    MatDesc* dm = p->d_mats;
+    double4* parts = p->d_parts;
+    int algo = o.algo, plain = o.plain ? 1 : 0;
+    double2* outp = nullptr;
+    push_arg(k, dm);
+    push_arg(k, parts);
+    push_arg(k, algo);
+    push_arg(k, plain);
+    push_arg(k, outp);
+    seal_args(k, {sizeof(dm), sizeof(parts), sizeof(algo), sizeof(plain), sizeof(outp)});
+    k.params.func = const_cast<void*>(finalize_batched_kernel());
+    k.params.gridDim = dim3((unsigned)batch);
+    k.params.blockDim = dim3(64);
+    k.params.sharedMemBytes = 0;
+    if ((e = add(std::move(k))) != hipSuccess) return e;
+    p->fin_idx = (int)p->nodes.size() - 1;
+  }
+  return hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+}
+
+int plan_build(const int32_t* n_host, const int64_t* off_host, int64_t batch, const Opts& o, const int32_t* c_force,
+               hipStream_t st, PlanImpl** out) {
+  auto* p = new PlanImpl;
+  hipGetDevice(&p->dev);
+  p->algo = o.algo;
+  p->plain = o.plain;
+  p->batch = batch;
+  p->n.assign(n_host, n_host + batch);
+  p->off.resize(batch);
+  p->c.resize(batch);
+  int64_t run = 0;
+  for (int64_t b = 0; b < batch; ++b) {
+    p->off[b] = off_host ? off_host[b] : run;
+    run += (int64_t)p->n[b] * p->n[b];
+  }
+  // chunk lengths
+  std::map<int, int> chosen;
+  for (int64_t b = 0; b < batch; ++b) {
+    const int n = p->n[b];
+    if (n == 0) {
+      p->c[b] = 0;
+      continue;
+    }
+    if (c_force) {
+      p->c[b] = c_force[b];
+      continue;
+    }
+    auto it = chosen.find(n);
+    if (it == chosen.end()) {
+      int c = 0;
+      if (o.chunk_log2 > 0) {
+        c = o.chunk_log2;
+      } else {
+        int rc = tuned_chunk(n, o.algo, o.plain, st, &c);
+        if (rc) {
+          destroy_impl(p);
+          return rc;
+        }
+      }
+      const int nb = gray_bits(n, o.algo);
+      c = std::max(min_chunk_log2(nb), std::min(c, nb));
+      it = chosen.emplace(n, c).first;
+    }
+    p->c[b] = it->second;
+  }
+  // order: bucket (largest first), then n descending, then batch index
+  std::vector<int64_t> order(batch);
+  for (int64_t b = 0; b < batch; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return p->n[x] > p->n[y]; });
+  // descriptors, tables, items
+  std::vector<MatDesc> mats(batch);
+  std::vector<WorkItem> items;
+  std::vector<std::pair<int64_t, int64_t>> bucket_items(NBUCKETS, {-1, -1});
+  size_t tab_elems = 0;
+  for (int64_t s = 0; s < batch; ++s) {
+    const int64_t b = order[s];
+    const int n = p->n[b];
+    MatDesc& m = mats[s];
+    m.a_off = p->off[b];
+    m.lda = n;
+    m.tab = reinterpret_cast<double2*>((uintptr_t)(tab_elems * sizeof(double2)));  // relocated below
+    m.n = n;
+    m.c = p->c[b];
+    m.out_index = b;
+    tab_elems += table_elems(n);
+    const int64_t first = (int64_t)items.size();
+    if (n > 0) {
+      const int bk = bucket_of(n);
+      const int nb = gray_bits(n, o.algo);
+      const uint64_t nchunks = (uint64_t)1 << (nb - m.c);
+      const int64_t nsuper = (int64_t)((nchunks + 63) / 64);
+      for (int64_t s0 = 0; s0 < nsuper; s0 += 4) {
+        WorkItem w;
+        w.mat = (int32_t)s;
+        w.rounds = (int32_t)std::min<int64_t>(4, nsuper - s0);
+        w.super0 = s0;
+        items.push_back(w);
+      }
+      auto& bi = bucket_items[bk];
+      if (bi.first < 0) bi.first = first;
+      bi.second = (int64_t)items.size();
+    }
+    m.part_begin = first * 4;
+    m.part_end = (int64_t)items.size() * 4;
+  }
+  p->n_items = (int64_t)items.size();
+  // one device allocation for everything the graph touches
+  const size_t sz_mats = align256(batch * sizeof(MatDesc));
+  const size_t sz_items = align256(std::max<size_t>(1, items.size()) * sizeof(WorkItem));
+  const size_t sz_cnt = align256(NBUCKETS * sizeof(uint32_t));
+  const size_t sz_parts = align256(std::max<size_t>(1, items.size() * 4) * sizeof(double4));
+  const size_t sz_tabs = align256(std::max<size_t>(1, tab_elems) * sizeof(double2));
+  hipError_t e = hipMalloc(&p->dmem, sz_mats + sz_items + sz_cnt + sz_parts + sz_tabs);
+  if (e != hipSuccess) {
+    destroy_impl(p);
+    return fail(PH_ENOMEM, "plan workspace: %s", hipGetErrorString(e));
+  }
+  char* q = p->dmem;
+  p->d_mats = reinterpret_cast<MatDesc*>(q);
+  q += sz_mats;
+  p->d_items = reinterpret_cast<WorkItem*>(q);
+  q += sz_items;
+  p->d_counters = reinterpret_cast<uint32_t*>(q);
+  q += sz_cnt;
+  p->d_parts = reinterpret_cast<double4*>(q);
+  q += sz_parts;
+  p->d_tabs = reinterpret_cast<double2*>(q);
+  for (auto& m : mats) m.tab = p->d_tabs + reinterpret_cast<uintptr_t>(m.tab) / sizeof(double2);
+  e = hipMemcpy(p->d_mats, mats.data(), batch * sizeof(MatDesc), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !items.empty())
+    e = hipMemcpy(p->d_items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    destroy_impl(p);
+    return hip_fail(e, "plan upload");
+  }
+  e = build_graph(p, o, bucket_items);
+  if (e != hipSuccess) {
+    destroy_impl(p);
+    return hip_fail(e, "plan graph");
+  }
+  *out = p;
+  return PH_OK;
+}
+
+// Point the prep node at `a` and the finalize node at `out`.
+static hipError_t set_io(PlanImpl* p, const double2* a, double2* out) {
+  hipError_t e = hipSuccess;
+  if (p->prep_idx >= 0 && a != p->last_a) {
+    KernelNode& k = p->nodes[p->prep_idx];
+    std::memcpy(k.argv[1], &a, sizeof(a));
+    e = hipGraphExecKernelNodeSetParams(p->exec, k.node, &k.params);
+    if (e != hipSuccess) return e;
+    p->last_a = a;
+  }
+  if (p->fin_idx >= 0 && out != p->last_out) {
+    KernelNode& k = p->nodes[p->fin_idx];
+    std::memcpy(k.argv[4], &out, sizeof(out));
+    e = hipGraphExecKernelNodeSetParams(p->exec, k.node, &k.params);
+    if (e != hipSuccess) return e;
+    p->last_out = out;
+  }
+  return e;
+}
+
+int plan_exec(PlanImpl* p, const double2* a, double2* out, hipStream_t st) {
+  hipError_t e = set_io(p, a, out);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphExecKernelNodeSetParams");
+  e = hipGraphLaunch(p->exec, st);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  p->launched = true;
+  p->last_stream = st;
+  return PH_OK;
+}
+
+static int check_batch_args(const int32_t* n_host, int64_t batch) {
+  if (batch < 0) return fail(PH_EINVAL, "batch=%lld < 0", (long long)batch);
+  if (batch > ((int64_t)1 << 30)) return fail(PH_EINVAL, "batch=%lld too large", (long long)batch);
+  if (batch > 0 && !n_host) return fail(PH_EINVAL, "n_host is NULL");
+  for (int64_t b = 0; b < batch; ++b) {
+    if (n_host[b] < 0) return fail(PH_EINVAL, "n[%lld]=%d < 0", (long long)b, n_host[b]);
+    if (n_host[b] > PH_NMAX) return fail(PH_ERANGE, "n[%lld]=%d > %d", (long long)b, n_host[b], PH_NMAX);
+  }
+  return PH_OK;
+}
+
+}  // namespace ph
+
+using namespace ph;
+
+extern "C" int ph_plan_create(const int32_t* n_host, const int64_t* offsets_host, int64_t batch, const ph_opts* opt,
+                              void* stream, void** plan) {
+  Opts o;
+  int rc = read_opts(opt, &o);
+  if (rc) return rc;
+  if (!plan) return fail(PH_EINVAL, "plan is NULL");
+  *plan = nullptr;
+  if ((rc = check_batch_args(n_host, batch))) return rc;
+  if (offsets_host)
+    for (int64_t b = 0; b < batch; ++b)
+      if (offsets_host[b] < 0) return fail(PH_EINVAL, "offsets[%lld] < 0", (long long)b);
+  if (num_cus() <= 0) return PH_EUNSUPPORTED;
+  PlanImpl* p = nullptr;
+  rc = plan_build(n_host, offsets_host, batch, o, nullptr, (hipStream_t)stream, &p);
+  if (rc) return rc;
+  *plan = p;
+  return PH_OK;
+}
+
+extern "C" int ph_plan_execute(void* plan, const ph_c128* A_packed, ph_c128* out, void* stream) {
+  if (!plan) return fail(PH_EINVAL, "plan is NULL");
+  auto* p = static_cast<PlanImpl*>(plan);
+  if (p->batch > 0 && (!A_packed || !out)) return fail(PH_EINVAL, "A_packed or out is NULL");
+  int dev = 0;
+  hipGetDevice(&dev);
+  if (dev != p->dev) return fail(PH_EINVAL, "plan was created on device %d, current device is %d", p->dev, dev);
+  return plan_exec(p, reinterpret_cast<const double2*>(A_packed), reinterpret_cast<double2*>(out),
+                   (hipStream_t)stream);
+}
+
+extern "C" int ph_plan_destroy(void* plan) {
+  if (!plan) return fail(PH_EINVAL, "plan is NULL");
+  destroy_impl(static_cast<PlanImpl*>(plan));
+  return PH_OK;
+}
+
+// ph_perm_batched keeps the last few plans (per device, stream, options and
+// sizes) so that repeated calls with the same shapes skip planning and stay
+// asynchronous.
+namespace ph {
+struct CacheKey {
+  int dev;
+  hipStream_t st;
+  int algo, plain, chunk, waves;
+  std::vector<int32_t> n;
+  std::vector<int64_t> off;
+  bool operator==(const CacheKey& o) const {
+    return dev == o.dev && st == o.st && algo == o.algo && plain == o.plain && chunk == o.chunk &&
+           waves == o.waves && n == o.n && off == o.off;
+  }
+};
+static std::mutex g_cache_mu;
+static std::vector<std::pair<CacheKey, PlanImpl*>> g_plans;  // most recent last
+constexpr size_t PLAN_CACHE = 4;
+}  // namespace ph
+
+extern "C" int ph_perm_batched(const ph_c128* A_packed, const int64_t* offsets_host, const int32_t* n_host,
+                               int64_t batch, ph_c128* out, const ph_opts* opt, void* stream) {
+  Opts o;
+  int rc = read_opts(opt, &o);
+  if (rc) return rc;
+  if ((rc = check_batch_args(n_host, batch))) return rc;
+  if (batch > 0 && (!A_packed || !out)) return fail(PH_EINVAL, "A_packed or out is NULL");
+  CacheKey key;
+  hipGetDevice(&key.dev);
+  key.st = (hipStream_t)stream;
+  key.algo = o.algo;
+  key.plain = o.plain;
+  key.chunk = o.chunk_log2;
+  key.waves = o.waves;
+  key.n.assign(n_host, n_host + batch);
+  if (offsets_host) key.off.assign(offsets_host, offsets_host + batch);
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  PlanImpl* p = nullptr;
+  for (size_t i = 0; i < g_plans.size(); ++i) {
+    if (g_plans[i].first == key) {
+      auto hit = g_plans[i];
+      g_plans.erase(g_plans.begin() + i);
+      g_plans.push_back(hit);
+      p = hit.second;
+      break;
+    }
+  }
+  if (!p) {
+    void* h = nullptr;
+    rc = ph_plan_create(n_host, offsets_host, batch, opt, stream, &h);
+    if (rc) return rc;
+    p = static_cast<PlanImpl*>(h);
+    if (g_plans.size() >= PLAN_CACHE) {
+      destroy_impl(g_plans.front().second);  // waits for its stream first
+      g_plans.erase(g_plans.begin());
+    }
+    g_plans.emplace_back(std::move(key), p);
+  }
+  return ph_plan_execute(p, A_packed, out, stream);
+}

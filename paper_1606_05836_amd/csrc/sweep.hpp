@@ -189,17 +189,20 @@ __device__ __forceinline__ void flush(dd2& acc, double2& sb, bool plain, bool ac
   sb = make_double2(0.0, 0.0);
 }
 
-// Per-wave sweep state: the DPP-resident update columns.
-template <int N, int ALGO>
+// Per-wave sweep state: the DPP-resident update columns (DR of them; a
+// caller with more live state of its own may ask for fewer than Shape::D).
+template <int N, int ALGO, int DR = Shape<N, ALGO>::D>
 struct Resident {
   using S = Shape<N, ALGO>;
-  double col[S::D > 0 ? S::D : 1][S::NP];
+  static_assert(DR <= S::D, "resident columns exceed the register budget");
+  static constexpr int D = DR;
+  double col[DR > 0 ? DR : 1][S::NP];
 
   // Load from the LDS table (after the block barrier).
   __device__ __forceinline__ void load(const double2* T) {
     const int l16 = threadIdx.x & 15;
 #pragma unroll
-    for (int b = 0; b < S::D; ++b) {
+    for (int b = 0; b < DR; ++b) {
       const double* c = reinterpret_cast<const double*>(T + (b + S::OFF) * N);
 #pragma unroll
       for (int p = 0; p < S::NP; ++p) {
@@ -212,8 +215,8 @@ struct Resident {
 
 // One lane sweeps the chunk [k0, k0 + 2^c) and folds it into acc.
 // Requires LOGU <= c <= nb (c == 0 only when the formula has a single term).
-template <int N, int ALGO>
-__device__ __forceinline__ void sweep_chunk(uint64_t k0, int c, const Resident<N, ALGO>& res, const double2* T,
+template <int N, int ALGO, int DR>
+__device__ __forceinline__ void sweep_chunk(uint64_t k0, int c, const Resident<N, ALGO, DR>& res, const double2* T,
                                             dd2& acc, bool plain, bool active) {
   using S = Shape<N, ALGO>;
   constexpr int LOGU = S::LOGU;
@@ -241,7 +244,7 @@ __device__ __forceinline__ void sweep_chunk(uint64_t k0, int c, const Resident<N
           const uint64_t k = k0 + tb + s;
           sg = ((k >> (b + 1)) & 1) ? mone : one;
         }
-        if constexpr (b < S::D)
+        if constexpr (b < DR)
           add_resident<N, S::NP>(r, res.col[b], sg);
         else
           fma_lds<N>(r, sg, T + (b + S::OFF) * N);

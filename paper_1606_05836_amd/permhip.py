@@ -60,7 +60,7 @@ def lib() -> ctypes.CDLL:
     L.ph_boson_probs.argtypes = [vp, i32, i64, P(ctypes.c_int32), i32, P(ctypes.c_int32), i64, dp, op, vp]
     L.ph_boson_probs_grad.argtypes = [vp, i32, i64, P(ctypes.c_int32), i32, P(ctypes.c_int32), i64, dp, dp, vp,
                                       i64, op, vp]
-    L.ph_fp64_peak.argtypes = [i64, P(ctypes.c_double), vp]
+    L.ph_fp64_peak.argtypes = [i64, P(ctypes.c_double), P(ctypes.c_double), vp]
     L.ph_last_error.restype = ctypes.c_char_p
     L.ph_last_error.argtypes = []
     L.ph_version.restype = ctypes.c_int
@@ -255,13 +255,14 @@ def boson_probs_grad(u: torch.Tensor, in_modes, patterns, weights: torch.Tensor 
     return probs, du
 
 
-def fp64_peak(iters: int = 1 << 16, device=None) -> float:
-    """Achieved FP64 FMA GFLOP/s of the device (microbenchmark kernel)."""
+def fp64_peak(iters: int = 1 << 14, device=None):
+    """(GFLOP/s, sustained shader clock in MHz) of the FP64 FMA microbenchmark."""
     g = ctypes.c_double(0.0)
+    mhz = ctypes.c_double(0.0)
     dev = torch.device(device or "cuda")
     st = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
-    check(lib().ph_fp64_peak(int(iters), ctypes.byref(g), st))
-    return g.value
+    check(lib().ph_fp64_peak(int(iters), ctypes.byref(g), ctypes.byref(mhz), st))
+    return g.value, mhz.value
 
 
 def version() -> int:
