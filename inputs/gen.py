@@ -41,7 +41,9 @@ def haar(m: int, seed: int) -> np.ndarray:
 
 def submatrix(u: np.ndarray, rows, cols) -> np.ndarray:
     """Contiguous copy of u[rows][:, cols] (rows/cols may repeat)."""
-    return np.ascontiguousarray(u[np.asarray(rows)][:, np.asarray(cols)], dtype=np.complex128)
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    return np.ascontiguousarray(u[rows][:, cols], dtype=np.complex128)
 
 
 def int_matrix(n: int, lo: int, hi: int, seed: int) -> np.ndarray:

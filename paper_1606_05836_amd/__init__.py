@@ -15,3 +15,4 @@ from .permhip import (  # noqa: F401
     perm_grad,
     version,
 )
+from .autograd import PermFn, permanent  # noqa: F401

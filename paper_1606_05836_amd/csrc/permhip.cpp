@@ -218,10 +218,6 @@ int perm_single(const double2* A, int n, int64_t lda, double2* out, const Opts& 
 
 #define PH_TODO(name) return fail(PH_EUNSUPPORTED, name " is not implemented in this build")
 
-extern "C" int ph_perm_grad(const ph_c128*, int32_t, int64_t, const ph_c128*, ph_c128*, ph_c128*, const ph_opts*,
-                            void*) {
-  PH_TODO("ph_perm_grad");
-}
 extern "C" int ph_boson_probs(const ph_c128*, int32_t, int64_t, const int32_t*, int32_t, const int32_t*, int64_t,
                               double*, const ph_opts*, void*) {
   PH_TODO("ph_boson_probs");

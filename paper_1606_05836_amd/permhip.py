@@ -168,10 +168,13 @@ def perm_batched(mats: Sequence[torch.Tensor] | torch.Tensor, algo="glynn", accu
     if isinstance(mats, torch.Tensor):
         if mats.dim() != 3 or mats.shape[1] != mats.shape[2]:
             raise ValueError("expected (batch, n, n)")
-        mats = list(mats)
-    for m in mats:
-        _need_c128_cuda("matrix", m)
-    ns, flat = _pack(mats)
+        _need_c128_cuda("mats", mats)
+        ns, flat = [int(mats.shape[1])] * int(mats.shape[0]), mats.contiguous().reshape(-1)
+        mats = [mats] if mats.shape[0] else []
+    else:
+        for m in mats:
+            _need_c128_cuda("matrix", m)
+        ns, flat = _pack(mats)
     batch = len(ns)
     dev = mats[0].device if batch else torch.device("cuda")
     out = torch.empty(batch, dtype=torch.complex128, device=dev)
