@@ -15,4 +15,4 @@ from .permhip import (  # noqa: F401
     perm_grad,
     version,
 )
-from .autograd import PermFn, permanent  # noqa: F401
+from .autograd import BosonProbsFn, PermFn, boson_probabilities, permanent  # noqa: F401

@@ -39,3 +39,33 @@ class PermFn(torch.autograd.Function):
 def permanent(a: torch.Tensor) -> torch.Tensor:
     """Differentiable permanent of (..., n, n) complex128 CUDA matrices."""
     return PermFn.apply(a)
+
+
+class BosonProbsFn(torch.autograd.Function):
+    """Eq. (1) probabilities Pr[S -> T_p] as a differentiable function of U.
+
+    Backward: ph_boson_probs_grad with the upstream gradient as the pattern
+    weights gives dL/dU[:, S_k] per input photon k; photons that share an
+    input mode add into the same column of U's gradient."""
+
+    @staticmethod
+    def forward(ctx, u: torch.Tensor, in_modes, patterns) -> torch.Tensor:
+        ctx.save_for_backward(u)
+        ctx.in_modes = in_modes
+        ctx.patterns = patterns
+        return _p.boson_probs(u, in_modes, patterns)
+
+    @staticmethod
+    def backward(ctx, g: torch.Tensor):
+        (u,) = ctx.saved_tensors
+        _, du = _p.boson_probs_grad(u, ctx.in_modes, ctx.patterns, weights=g)
+        cols = torch.as_tensor([int(x) for x in ctx.in_modes], dtype=torch.int64, device=u.device)
+        gu = torch.zeros_like(u)
+        gu.index_add_(1, cols, du)
+        return gu, None, None
+
+
+def boson_probabilities(u: torch.Tensor, in_modes, patterns) -> torch.Tensor:
+    """Differentiable Eq. (1) probabilities of output patterns (rows of
+    `patterns`) for input modes `in_modes` of the m x m complex128 CUDA unitary u."""
+    return BosonProbsFn.apply(u, in_modes, patterns)

@@ -9,6 +9,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -81,16 +82,18 @@ struct Buf {
   void* p = nullptr;
   size_t cap = 0;
 };
-static std::map<std::pair<int, hipStream_t>, Buf> g_ws;
+static std::map<std::tuple<int, hipStream_t, int>, Buf> g_ws;
 
-// Library-owned scratch for one (device, stream); grown on demand.  Work on
-// one stream is ordered, so reuse across calls on that stream is safe.
-int workspace(hipStream_t st, size_t bytes, void** out) {
+// Library-owned scratch for one (device, stream, slot); grown on demand.
+// Work on one stream is ordered, so reuse across calls on that stream is
+// safe.  Slot 0 belongs to the permanent kernels; a caller that composes them
+// keeps its own buffers in another slot.
+int workspace_slot(hipStream_t st, size_t bytes, int slot, void** out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   std::lock_guard<std::mutex> lk(g_mu);
-  Buf& b = g_ws[{dev, st}];
+  Buf& b = g_ws[{dev, st, slot}];
   if (b.cap < bytes) {
     if (b.p) {
       // the old buffer may still be in use by queued work on this stream
@@ -108,6 +111,8 @@ int workspace(hipStream_t st, size_t bytes, void** out) {
   *out = b.p;
   return PH_OK;
 }
+
+int workspace(hipStream_t st, size_t bytes, void** out) { return workspace_slot(st, bytes, 0, out); }
 
 // ------------------------------------------------------------------ options
 
@@ -214,15 +219,3 @@ int perm_single(const double2* A, int n, int64_t lda, double2* out, const Opts& 
 
 }  // namespace ph
 
-// ----------------------------------------------------- not yet implemented
-
-#define PH_TODO(name) return fail(PH_EUNSUPPORTED, name " is not implemented in this build")
-
-extern "C" int ph_boson_probs(const ph_c128*, int32_t, int64_t, const int32_t*, int32_t, const int32_t*, int64_t,
-                              double*, const ph_opts*, void*) {
-  PH_TODO("ph_boson_probs");
-}
-extern "C" int ph_boson_probs_grad(const ph_c128*, int32_t, int64_t, const int32_t*, int32_t, const int32_t*,
-                                   int64_t, const double*, double*, ph_c128*, int64_t, const ph_opts*, void*) {
-  PH_TODO("ph_boson_probs_grad");
-}

@@ -18,6 +18,7 @@ int fail(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 int read_opts(const ph_opts* o, Opts* r);
 int workspace(hipStream_t st, size_t bytes, void** out);
+int workspace_slot(hipStream_t st, size_t bytes, int slot, void** out);
 int num_cus();
 int gray_bits(int n, int algo);
 int min_chunk_log2(int nb);

@@ -11,6 +11,7 @@ import ctypes
 import os
 from typing import Sequence
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -210,51 +211,64 @@ def perm_grad(a: torch.Tensor, grad_out: torch.Tensor | None = None, accum="dd",
     return p, ga
 
 
-def _modes(x, name):
-    arr = [int(v) for v in (x.tolist() if hasattr(x, "tolist") else x)]
-    return arr
+def _modes(in_modes, patterns, m: int):
+    """Host int32 copies of the mode lists: (in_modes (n,), patterns (npat, n))."""
+    ins = np.ascontiguousarray(np.asarray(in_modes, dtype=np.int64).reshape(-1).astype(np.int32))
+    n = ins.shape[0]
+    pats = np.asarray(patterns, dtype=np.int64)
+    if pats.ndim == 1 and pats.size == 0:
+        pats = pats.reshape(0, n)
+    if pats.ndim != 2 or pats.shape[1] != n:
+        raise ValueError(f"patterns must have shape (n_patterns, {n})")
+    pats = np.ascontiguousarray(pats.astype(np.int32))
+    return ins, pats
+
+
+def _i32p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _need_square_u(u: torch.Tensor):
+    _need_c128_cuda("u", u)
+    if u.dim() != 2 or u.shape[0] != u.shape[1]:
+        raise ValueError("u must be an m x m matrix")
+    return u if u.stride(1) == 1 else u.contiguous()
 
 
 def boson_probs(u: torch.Tensor, in_modes, patterns, algo="glynn", accum="dd") -> torch.Tensor:
-    """Eq. (1) probabilities for each output pattern (rows of `patterns`)."""
-    _need_c128_cuda("u", u)
+    """Eq. (1) probabilities Pr[S -> T_p] for each row T_p of `patterns`.
+
+    u: m x m complex128 CUDA tensor indexed [output mode, input mode];
+    in_modes: the n input modes (repeats for multi-photon inputs);
+    patterns: (n_patterns, n) output modes (repeats for collisions)."""
+    u = _need_square_u(u)
     m = u.shape[0]
-    if u.stride(1) != 1:
-        u = u.contiguous()
-    ins = _modes(in_modes, "in_modes")
-    pats = [_modes(p, "pattern") for p in (patterns.tolist() if hasattr(patterns, "tolist") else patterns)]
-    n = len(ins)
-    npat = len(pats)
-    flat = [v for p in pats for v in p]
-    if any(len(p) != n for p in pats):
-        raise ValueError("every pattern needs n entries")
+    ins, pats = _modes(in_modes, patterns, m)
+    n, npat = ins.shape[0], pats.shape[0]
     probs = torch.empty(npat, dtype=torch.float64, device=u.device)
     o = opts(algo, accum)
-    check(lib().ph_boson_probs(_ptr(u), m, u.stride(0), (ctypes.c_int32 * max(1, n))(*ins), n,
-                               (ctypes.c_int32 * max(1, len(flat)))(*flat), npat, _ptr(probs), ctypes.byref(o),
-                               _stream(u)))
+    check(lib().ph_boson_probs(_ptr(u), m, u.stride(0), _i32p(ins), n, _i32p(pats), npat, _ptr(probs),
+                               ctypes.byref(o), _stream(u)))
     return probs
 
 
 def boson_probs_grad(u: torch.Tensor, in_modes, patterns, weights: torch.Tensor | None = None, accum="dd"):
-    """(probs, dU) with dU[:, k] = dL/dU[:, in_modes[k]], L = sum_p w_p Pr_p."""
-    _need_c128_cuda("u", u)
+    """(probs, dU): dU (m x n) holds dL/dU[:, in_modes[k]] in column k for
+    L = sum_p w_p Pr[S -> T_p] (PyTorch's conjugate-Wirtinger convention)."""
+    u = _need_square_u(u)
     m = u.shape[0]
-    if u.stride(1) != 1:
-        u = u.contiguous()
-    ins = _modes(in_modes, "in_modes")
-    pats = [_modes(p, "pattern") for p in (patterns.tolist() if hasattr(patterns, "tolist") else patterns)]
-    n, npat = len(ins), len(pats)
-    flat = [v for p in pats for v in p]
+    ins, pats = _modes(in_modes, patterns, m)
+    n, npat = ins.shape[0], pats.shape[0]
     probs = torch.empty(npat, dtype=torch.float64, device=u.device)
     du = torch.empty((m, n), dtype=torch.complex128, device=u.device)
     w = None
     if weights is not None:
         w = weights.to(device=u.device, dtype=torch.float64).contiguous()
+        if w.numel() != npat:
+            raise ValueError("weights needs one entry per pattern")
     o = opts("glynn", accum)
-    check(lib().ph_boson_probs_grad(_ptr(u), m, u.stride(0), (ctypes.c_int32 * max(1, n))(*ins), n,
-                                    (ctypes.c_int32 * max(1, len(flat)))(*flat), npat, _ptr(w), _ptr(probs),
-                                    _ptr(du), du.stride(0), ctypes.byref(o), _stream(u)))
+    check(lib().ph_boson_probs_grad(_ptr(u), m, u.stride(0), _i32p(ins), n, _i32p(pats), npat, _ptr(w),
+                                    _ptr(probs), _ptr(du), du.stride(0), ctypes.byref(o), _stream(u)))
     return probs, du
 
 

@@ -79,3 +79,41 @@ def test_python_binding_rejects_non_device_tensors():
         ph.perm(torch.zeros((3, 3), dtype=torch.complex128))
     with pytest.raises(TypeError):
         ph.perm(torch.zeros((3, 3), dtype=torch.float64))
+
+
+def test_boson_argument_errors_are_reported_before_any_device_work(L):
+    from paper_1606_05836_amd import permhip as P
+
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    I32 = ctypes.c_int32
+
+    def probs(m, ldu, ins, pats, npat, out=fake, u=fake):
+        n = len(ins)
+        a = (I32 * max(1, n))(*ins)
+        p = (I32 * max(1, len(pats)))(*pats)
+        return L.ph_boson_probs(u, m, ldu, a, n, p, npat, out, None, None)
+
+    def grad(m, ins, pats, npat, lddu, du=fake, o=None):
+        n = len(ins)
+        a = (I32 * max(1, n))(*ins)
+        p = (I32 * max(1, len(pats)))(*pats)
+        return L.ph_boson_probs_grad(fake, m, m, a, n, p, npat, None, None, du, lddu,
+                                     ctypes.byref(o) if o else None, None)
+
+    assert probs(4, 4, [0, 5], [0, 1], 1) == P.PH_EINVAL  # input mode >= m
+    assert b"in_modes[1]=5" in L.ph_last_error()
+    assert probs(4, 4, [0, 1], [0, -1], 1) == P.PH_EINVAL  # output mode < 0
+    assert probs(4, 3, [0, 1], [0, 1], 1) == P.PH_EINVAL  # ldu < m
+    assert probs(0, 4, [], [], 0) == P.PH_EINVAL  # m < 1
+    assert probs(4, 4, [0, 1], [0, 1], -1) == P.PH_EINVAL
+    assert probs(4, 4, [0, 1], [0, 1], 1, out=None) == P.PH_EINVAL
+    assert probs(4, 4, [0, 1], [0, 1], 1, u=None) == P.PH_EINVAL
+    big = list(range(P.PH_NMAX + 1))
+    assert probs(64, 64, big, big, 1) == P.PH_ERANGE
+    g = list(range(P.PH_NMAX_GRAD + 1))
+    assert grad(64, g, g, 1, 64) == P.PH_ERANGE
+    assert grad(4, [0, 1], [0, 1], 1, 1) == P.PH_EINVAL  # lddu < n
+    assert grad(4, [0, 1], [0, 1], 1, 2, du=None) == P.PH_EINVAL
+    assert grad(4, [], [], 0, 1) == P.PH_EINVAL  # the gradient needs n >= 1
+    assert grad(4, [0, 1], [0, 1], 1, 2, o=P.PhOpts(P.PH_RYSER, 0, 0, 0, 0)) == P.PH_EINVAL
+    assert b"PH_GLYNN" in L.ph_last_error()
