@@ -7,9 +7,15 @@ double-double outer sum -- one call of ph_perm with the input resident in HBM.
 
 Reported: Gray-code terms/s (whole job = one GPU), the sweep's achieved
 algorithmic FP64 rate against the chip's vector-FP64 peak, and the exact CPU
-oracle timed on a bounded sample of the same sweep on the host's cores.
+oracle timed on a bounded sample of the same sweep on the host's cores.  The
+same line carries, under "extras", the other two figures of the metric --
+batched permanents/s (4096 matrices, n uniform in 16..26, one graph replay)
+and the backward/forward time ratio (1024 matrices of n = 20) -- and the
+boson-sampling workload (U 900 x 900, 30 photons, 256 collision patterns):
+probabilities/s and the gradient's cost.
 
-usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 40] [--extras]
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 40]
+                       [--no-cpu] [--no-extras] [--copy-probe MiB]
 """
 from __future__ import annotations
 
@@ -86,6 +92,85 @@ def cpu_baseline(a, n: int, seconds: float = 15.0):
     }
 
 
+def _log(msg: str):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def _median(xs):
+    xs = sorted(xs)
+    k = len(xs)
+    return xs[k // 2] if k % 2 else 0.5 * (xs[k // 2 - 1] + xs[k // 2])
+
+
+def _event_ms(fn, reps, stream):
+    """Durations (ms) of `reps` calls of fn, each bracketed by HIP events on
+    the stream the library launches on."""
+    import torch
+
+    out = []
+    for _ in range(reps):
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        s.record(stream)
+        fn()
+        e.record(stream)
+        e.synchronize()
+        out.append(s.elapsed_time(e))
+    return out
+
+
+def extras(ph, dev, stream):
+    """Batched perms/s, the backward/forward ratio and the boson workload."""
+    import numpy as np
+    import torch
+
+    import inputs
+
+    res = {}
+    # 4096 permanents, n ~ U{16..26}, one persistent graph replay
+    ns, mats = inputs.config2_batch()
+    flat = torch.from_numpy(np.concatenate([m.reshape(-1) for m in mats])).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = ph.Plan([int(x) for x in ns], device=dev)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    out = plan(flat)
+    ms = _median(_event_ms(lambda: plan(flat, out), 7, stream))
+    terms = float(sum(1 << (int(n) - 1) for n in ns))
+    flops = float(sum((1 << (int(n) - 1)) * flops_per_term(int(n)) for n in ns))
+    _log(f"batched: {ms:.2f} ms per replay of 4096 permanents")
+    res["batched"] = {
+        "workload": "4096 permanents, n uniform in 16..26 (seed 21), rows of Haar(n^2, 2000+n) (seed 22)",
+        "perms_per_s": len(ns) / (ms / 1e3), "ms": ms, "terms_per_s": terms / (ms / 1e3),
+        "frac_fp64_peak": flops / (ms / 1e3) / 1e12 / PEAK_FP64_VECTOR_TFLOPS, "plan_s": plan_s,
+    }
+    plan.close()
+    # backward of L = |perm|^2 against the forward, 1024 matrices of n = 20
+    a4 = torch.from_numpy(inputs.config4_batch()).to(dev)
+    p4 = ph.perm_batched(a4)
+    g4 = 2 * p4
+    fwd = _median(_event_ms(lambda: ph.perm_batched(a4), 7, stream))
+    bwd = _median(_event_ms(lambda: ph.perm_grad(a4, grad_out=g4, want_perm=False), 5, stream))
+    _log(f"grad/fwd: {bwd:.2f} / {fwd:.2f} ms")
+    res["grad_fwd"] = {
+        "workload": "dL/dA of L = |perm(A)|^2, 1024 x (20 x 20) rows of Haar(400, 41) (seed 42)",
+        "fwd_ms": fwd, "grad_ms": bwd, "ratio": bwd / fwd,
+    }
+    # boson sampling: Eq. (1) probabilities and their gradient
+    u, ins, pats = inputs.config5_workload()
+    ud = torch.from_numpy(u).to(dev)
+    ph.boson_probs(ud, ins, pats)
+    pf = _median(_event_ms(lambda: ph.boson_probs(ud, ins, pats), 3, stream))
+    pg = _median(_event_ms(lambda: ph.boson_probs_grad(ud, ins, pats), 2, stream))
+    _log(f"boson: probs {pf:.1f} ms, gradient {pg:.1f} ms")
+    res["boson"] = {
+        "workload": "U = Haar(900, 51), inputs in modes 0..29, 256 collision patterns (seed 52)",
+        "probs_ms": pf, "probs_per_s": len(pats) / (pf / 1e3), "grad_ms": pg, "grad_fwd_ratio": pg / pf,
+    }
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,13 +181,15 @@ def main():
     ap.add_argument("--chunk-log2", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
+                    help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs on a single "
-              f"MI355X; multi-GPU sharding of the Gray range is described in DESIGN.md).", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the sweep runs on a single "
+              f"MI355X (sharding the Gray-code range across GPUs is a design note, not code).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import inputs
@@ -116,10 +203,19 @@ def main():
     out = torch.empty((), dtype=torch.complex128, device=dev)
     stream = torch.cuda.current_stream(dev)
     kw = dict(accum=args.accum, chunk_log2=args.chunk_log2, waves=args.waves)
+    if args.copy_probe > 0:
+        # a plain copy of known size: reads and writes copy_probe MiB of HBM
+        src = torch.ones(args.copy_probe << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         ph.perm(a, out=out, **kw)
     torch.cuda.synchronize()
+    _log(f"n={n}: {args.warmup} warm-up call(s) done")
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -130,6 +226,7 @@ def main():
         ends[i].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    _log(f"n={n}: {args.steps} timed step(s) in {wall:.2f} s")
     per_launch_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
     ms = sum(per_launch_ms) / len(per_launch_ms)
     terms = float(1 << (n - 1))
@@ -138,7 +235,7 @@ def main():
     result = complex(out.cpu())
 
     line = {
-        "metric": f"Gray-code terms/s (n={n} c128)",
+        "metric": "Gray-code terms/s (n=40 c128) as % FP64 peak; batched perms/s; grad/fwd ratio",
         "value": value,
         "unit": "terms/s",
         "n_gpus": 1,
@@ -167,10 +264,11 @@ def main():
         "wall_s": wall,
         "result": [result.real, result.imag],
     }
+    if not args.no_extras:
+        line["extras"] = extras(ph, dev, stream)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(a_host, n)
     print(json.dumps(line), flush=True)
-    _ = np
 
 
 if __name__ == "__main__":
