@@ -16,6 +16,7 @@ probabilities/s and the gradient's cost.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 40]
                        [--no-cpu] [--no-extras] [--copy-probe MiB]
+       python bench.py --precision 40,44   (precision study only)
 """
 from __future__ import annotations
 
@@ -171,6 +172,69 @@ def extras(ph, dev, stream):
     return res
 
 
+def _stored_exact():
+    """Exact permanents committed under tests/golden (written by the oracle):
+    name -> (n, sha256 of the input bytes, complex value)."""
+    from fractions import Fraction
+
+    out = {}
+    with open(os.path.join(ROOT, "tests", "golden", "haar_perms.txt")) as f:
+        for line in f:
+            if not line.strip() or line.startswith("#"):
+                continue
+            name, n, sha, e, re, im = line.split()
+            den = 1 << int(e)
+            out[name] = (int(n), sha, complex(Fraction(int(re), den)) + 1j * float(Fraction(int(im), den)))
+    return out
+
+
+def precision(ph, dev, large):
+    """Relative error of every (formula, outer sum) combination against the
+    stored exact values (n = 20..30), and the dd/plain and Glynn/Ryser
+    differences at the sizes no exact value exists for."""
+    import torch
+
+    import inputs
+
+    def run(a, algo, accum):
+        t = torch.from_numpy(a).to(dev)
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        s.record()
+        v = ph.perm(t, algo=algo, accum=accum)
+        e.record()
+        e.synchronize()
+        return complex(v.cpu()), s.elapsed_time(e)
+
+    rows = []
+    for name, (n, sha, exact) in sorted(_stored_exact().items(), key=lambda kv: kv[1][0]):
+        a = inputs.config1_haar20() if name == "config1_haar20" else inputs.config3_matrix(n)
+        if inputs.sha256_of(a) != sha:
+            raise RuntimeError(f"{name}: input bytes differ from the stored ones")
+        row = {"name": name, "n": n}
+        for algo in ("glynn", "ryser"):
+            for accum in ("dd", "plain"):
+                v, _ = run(a, algo, accum)
+                row[f"{algo}_{accum}"] = abs(v - exact) / abs(exact)
+        rows.append(row)
+        _log(f"precision: {name} done")
+    big = []
+    for n in large:
+        a = inputs.config3_matrix(n)
+        gd, t_gd = run(a, "glynn", "dd")
+        _log(f"precision: n={n} glynn dd {t_gd / 1e3:.1f} s")
+        gp, t_gp = run(a, "glynn", "plain")
+        rec = {"n": n, "glynn_dd": [gd.real, gd.imag], "glynn_dd_ms": t_gd, "glynn_plain_ms": t_gp,
+               "rel_diff_glynn_dd_vs_plain": abs(gp - gd) / abs(gd)}
+        if n <= 40:
+            rd, t_rd = run(a, "ryser", "dd")
+            rec["ryser_dd_ms"] = t_rd
+            rec["rel_diff_ryser_vs_glynn"] = abs(rd - gd) / abs(gd)
+        big.append(rec)
+        _log(f"precision: n={n} done")
+    return {"against_exact": rows, "large_n": big}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +248,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
                     help="run one plain device copy of this size first (counter calibration)")
+    ap.add_argument("--precision", default="", metavar="N,N",
+                    help="print only the precision study, with these large sizes (e.g. 40,44)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the sweep runs on a single "
@@ -203,6 +269,10 @@ def main():
     out = torch.empty((), dtype=torch.complex128, device=dev)
     stream = torch.cuda.current_stream(dev)
     kw = dict(accum=args.accum, chunk_log2=args.chunk_log2, waves=args.waves)
+    if args.precision:
+        large = [int(x) for x in args.precision.split(",") if x.strip() and int(x) > 0]
+        print(json.dumps({"precision": precision(ph, dev, large)}), flush=True)
+        return
     if args.copy_probe > 0:
         # a plain copy of known size: reads and writes copy_probe MiB of HBM
         src = torch.ones(args.copy_probe << 17, dtype=torch.float64, device=dev)
