@@ -7,7 +7,7 @@ Pr[S -> T] = |Per(U_{S,T})|^2 / (s_1! ... s_m! t_1! ... t_m!), where U is the
 m x m unitary of the network indexed [output mode, input mode] and U_{S,T} is
 the n x n submatrix whose rows are the output modes of T, each repeated t_j
 times, and whose columns are the input modes of S, each repeated s_i times.
-(The paper only says the submatrix is "derived from U"; this is the standard
+(The paper states only that the submatrix comes from U; this is the standard
 reading and the one the tests fix with the completeness sum below.)
 
 Two independent exact routes to Per(U_{S,T}):
