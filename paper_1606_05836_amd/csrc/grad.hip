@@ -8,13 +8,14 @@
 // new is (1) the leave-one-out products q_i and (2) collecting
 // w_i(t) = s_t q_i(t) into all n columns without O(n^2) work per term.
 //
-// (1) A term is split over a quad of four lanes; lane `sigma` of the quad
-//     owns rows [sigma*M, sigma*M + M).  Each lane forms suffix products of
-//     its rows, the quad exchanges the partial products with DPP quad
-//     permutes (P_other = product of the other three lanes' rows), and a
-//     prefix pass started from P_other yields q_i for its rows.  Splitting
-//     the rows keeps the per-lane state (row sums, suffix products, running
-//     sums, stored columns) in the register file.
+// (1) A term is split over a group of H lanes (H = 4 or 8); lane `sigma` of
+//     the group owns rows [sigma*M, sigma*M + M).  Each lane forms the suffix
+//     products of its rows, the group exchanges partial products with DPP
+//     lane permutes (quad xor 1, xor 2, then the half-row mirror for H = 8)
+//     to get O = the product of the other lanes' rows, and a running prefix
+//     started from s_t O yields s_t q_i for its rows, the last multiply fused
+//     into the accumulation.  Splitting the rows keeps the per-lane state
+//     (row sums, running sums, stored columns) in the register file.
 //
 // (2) Summation by parts.  In a chunk of L = 2^c terms with running sum
 //     W(t) = sum_{tau <= t} w(tau),
@@ -23,10 +24,14 @@
 //     that flip most often (Gray bits 0..K-1, used by 1 - 2^-K of all steps)
 //     are accumulated per lane in registers; a flip of any other column, and
 //     the boundary term of every column at the chunk end, is summed over the
-//     16 quads of the wavefront through LDS (each lane adds 16 values for one
-//     output) and added into the wavefront's n x n accumulator in global
-//     memory.  Every address of that accumulator is read and written by one
-//     fixed lane only, so program order is the only ordering needed.
+//     64/H groups of the wavefront through LDS (each lane adds 64/H values for
+//     one output) and added into the wavefront's n x ROWS accumulator in
+//     global memory.  Every address of that accumulator is read and written by
+//     one fixed lane only, so program order is the only ordering needed.
+//
+// The loop body holds one copy of the term code: the flipped bit ctz(t) is
+// the same on every lane, so the choice between a register-held column and a
+// boundary column is a scalar branch.
 //
 // The forward permanent comes out of the same sweep (prod of all rows).
 // All sums are in a fixed order, so results are bitwise reproducible.
@@ -44,44 +49,55 @@
 
 namespace ph {
 
-// quad permutes of a double: lane ^ 1 and lane ^ 2 within each quad
-__device__ __forceinline__ double quad_xor1(double v) {
+// lane permutes of a double: lane ^ 1, lane ^ 2 within each quad, and the
+// mirror within each half row of 8 lanes (lane i <-> 7 - i)
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
   const int lo = __double2loint(v), hi = __double2hiint(v);
-  return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false),
-                          __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false));
+  return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false),
+                          __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false));
 }
-__device__ __forceinline__ double quad_xor2(double v) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false),
-                          __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false));
+template <int CTRL>
+__device__ __forceinline__ double2 dpp_mov(double2 v) {
+  return make_double2(dpp_mov<CTRL>(v.x), dpp_mov<CTRL>(v.y));
 }
-__device__ __forceinline__ double2 quad_xor1(double2 v) { return make_double2(quad_xor1(v.x), quad_xor1(v.y)); }
-__device__ __forceinline__ double2 quad_xor2(double2 v) { return make_double2(quad_xor2(v.x), quad_xor2(v.y)); }
+constexpr int DPP_QUAD_XOR1 = 0xB1, DPP_QUAD_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141;
 
-// registers: stored columns per M (rows per lane)
+// Stored columns (K) and target wavefronts per SIMD per (rows per lane M,
+// lanes per term H).
 #ifndef PH_GRAD_K
-#define PH_GRAD_K(M) ((M) == 1 ? 1 : ((M) <= 5 ? 2 : 1))
+#define PH_GRAD_K(M, H) ((H) == 8 ? ((M) <= 2 ? 4 : 3) : ((M) == 1 ? 1 : ((M) <= 5 ? 2 : 1)))
 #endif
 #ifndef PH_GRAD_WAVES
-#define PH_GRAD_WAVES(M) ((M) <= 1 ? 4 : ((M) <= 3 ? 3 : 2))
+#define PH_GRAD_WAVES(M, H) ((H) == 8 ? ((M) <= 2 ? 3 : 2) : ((M) <= 1 ? 4 : ((M) <= 3 ? 3 : 2)))
+#endif
+// smallest n that uses H = 8 lanes per term
+#ifndef PH_GRAD_H8_MIN
+#define PH_GRAD_H8_MIN 21
 #endif
 
-template <int M>
+// terms summed in plain binary64 before each double-double accumulation
+constexpr uint32_t GRAD_FLUSH = 16;
+
+template <int M, int H>
 struct GradShape {
-  static constexpr int K = PH_GRAD_K(M);
-  static constexpr int U = 1 << K;
-  static constexpr int ROWS = 4 * M;  // padded rows of the table
-  // Gray bits K..K+R-1 (the columns flipped at block boundaries most often)
-  // collect their quad sums in registers of the owning lane
+  static constexpr int K = PH_GRAD_K(M, H);
+  static constexpr int ROWS = H * M;  // padded rows of the table
+  static constexpr int NG = 64 / H;   // term groups per wavefront
+  // Gray bits K..K+R-1 (the boundary columns flipped most often) collect
+  // their group sums in registers of the owning lane
   static constexpr int R = 4;
-  // target wavefronts per SIMD (register budget 512 / WAVES per lane)
-  static constexpr int WAVES = PH_GRAD_WAVES(M);
+  static constexpr int WAVES = PH_GRAD_WAVES(M, H);
+  // LDS staging: lane l writes its M complex values at complex offset l * SS,
+  // SS = M rounded up to odd, so the 16-byte writes of eight consecutive
+  // lanes cover all 32 banks once and the reads are conflict-free
+  static constexpr int SS = M | 1;
 };
 
 struct GradArgs {
   const double2* tabs;  // per matrix: n columns x ROWS rows (zero padded)
   int n, c;
-  int64_t nsuper;       // super-chunks per matrix (16 chunks each)
+  int64_t nsuper;       // super-chunks per matrix (64/H chunks each)
   int s_per;            // units (slices) per matrix
   int64_t units;        // batch * s_per
   uint32_t* counter;
@@ -90,28 +106,21 @@ struct GradArgs {
   int plain;
 };
 
-template <int M>
+template <int M, int H>
 struct GradLane {
   double2 r[M];
   double2 W[M];
-  double2 G[GradShape<M>::K][M];
-  double2 colK[GradShape<M>::K][M];  // the lane's rows of columns 1..K
+  double2 G[GradShape<M, H>::K][M];
+  double2 colK[GradShape<M, H>::K][M];  // the lane's rows of columns 1..K
 };
 
-// LDS sum of wt * W over the 16 quads of the wavefront.  Lane o < 8M gets
-// output o -- row o / 2 of the quad's 4M rows, real part if o is even --
-// the other lanes get 0.  Staging: lane l writes its M complex values at
-// complex offset l * SS with SS = M rounded up to odd, so the 16-byte
-// writes of eight consecutive lanes cover all 32 banks once and the reads
-// (consecutive lanes, consecutive addresses) are conflict-free.
-template <int M>
-struct Stage {
-  static constexpr int SS = M | 1;  // complex entries per lane
-};
-
-template <int M>
-__device__ __forceinline__ double quad_sum(const double2 (&W)[M], double wt, double* stage) {
-  constexpr int SS = Stage<M>::SS;
+// Sum of wt * W over the groups of the wavefront, through LDS.  Lane
+// o < 2 ROWS gets output o -- row o / 2 of the group's ROWS rows, real part
+// if o is even -- the other lanes get 0.
+template <int M, int H>
+__device__ __forceinline__ double group_sum(const double2 (&W)[M], double wt, double* stage) {
+  using GS = GradShape<M, H>;
+  constexpr int SS = GS::SS;
   const int lane = threadIdx.x & 63;
   double2* st2 = reinterpret_cast<double2*>(stage);
 #pragma unroll
@@ -120,11 +129,11 @@ __device__ __forceinline__ double quad_sum(const double2 (&W)[M], double wt, dou
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   double s = 0.0;
-  if (lane < 8 * M) {
+  if (lane < 2 * GS::ROWS) {
     const int sig = lane / (2 * M), d = lane % (2 * M);
     const double* base = stage + 2 * sig * SS + d;
 #pragma unroll
-    for (int g = 0; g < 16; ++g) s += base[2 * 4 * SS * g];
+    for (int g = 0; g < GS::NG; ++g) s += base[2 * H * SS * g];
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -132,45 +141,53 @@ __device__ __forceinline__ double quad_sum(const double2 (&W)[M], double wt, dou
   return s;
 }
 
-// Adds a quad sum into the wavefront's accumulator column (global memory,
+// Adds a group sum into the wavefront's accumulator column (global memory,
 // owned entry by entry by the lanes that compute them).
-template <int M>
-__device__ __forceinline__ void quad_sum_add(const double2 (&W)[M], double wt, double* stage, double* gcol) {
-  const double s = quad_sum<M>(W, wt, stage);
+template <int M, int H>
+__device__ __forceinline__ void group_sum_add(const double2 (&W)[M], double wt, double* stage, double* gcol) {
+  const double s = group_sum<M, H>(W, wt, stage);
   const int lane = threadIdx.x & 63;
-  if (lane < 8 * M) gcol[lane] += s;
+  if (lane < 2 * GradShape<M, H>::ROWS) gcol[lane] += s;
 }
 
-// One term: leave-one-out products of the quad's rows, W += st q, and the
-// full product into sb (st = the term's sign).  The suffix products and the
-// prefix products of the lane's own rows are two independent chains; the
-// quad exchange then gives O = product of the other lanes' rows and
-// q_i = (O pre_i) suf_{i+1}, the last multiply fused into the W update.
-template <int M>
-__device__ __forceinline__ void grad_term(GradLane<M>& L, double st, double2& sb) {
-  double2 suf[M], pre[M];
+// Product of the rows owned by the other H - 1 lanes of the group, from each
+// lane's product of its own rows.
+template <int H>
+__device__ __forceinline__ double2 others_product(double2 own) {
+  const double2 p1 = dpp_mov<DPP_QUAD_XOR1>(own);  // partner lane
+  const double2 pair = cmul(own, p1);
+  const double2 pair2 = dpp_mov<DPP_QUAD_XOR2>(pair);  // the other pair of the quad
+  if constexpr (H == 4) {
+    return cmul(p1, pair2);
+  } else {
+    const double2 quad = cmul(pair, pair2);
+    const double2 quad2 = dpp_mov<DPP_HALF_MIRROR>(quad);  // the other quad of the 8
+    return cmul(cmul(p1, pair2), quad2);
+  }
+}
+
+// One term: W_i += st q_i for the lane's rows and the full product st P into
+// sb (st = the term's sign).  Suffix products of the own rows, the group
+// exchange for O, then a running prefix t_i = st O prod_{k<i} r_k with
+// q_i st = t_i suf_{i+1}, the last multiply fused into the W update.
+template <int M, int H>
+__device__ __forceinline__ void grad_term(GradLane<M, H>& L, double st, double2& sb) {
+  double2 suf[M];
   suf[M - 1] = L.r[M - 1];
 #pragma unroll
   for (int ii = M - 2; ii >= 0; --ii) suf[ii] = cmul(L.r[ii], suf[ii + 1]);
-  if constexpr (M > 1) {
-    pre[1] = L.r[0];
-#pragma unroll
-    for (int ii = 2; ii < M; ++ii) pre[ii] = cmul(pre[ii - 1], L.r[ii - 1]);
-  }
-  const double2 p1 = quad_xor1(suf[0]);
-  const double2 pair = cmul(suf[0], p1);
-  const double2 pair2 = quad_xor2(pair);
-  const double2 o = cmul(p1, pair2);  // product of the other three lanes' rows
+  const double2 o = others_product<H>(suf[0]);
   const double2 os = make_double2(st * o.x, st * o.y);
+  double2 t = os;
 #pragma unroll
   for (int ii = 0; ii < M; ++ii) {
-    const double2 t = ii == 0 ? os : cmul(os, pre[ii]);  // st * O * prefix
     if (ii < M - 1) {
       const double2 s1 = suf[ii + 1];
       L.W[ii].x = fma(t.x, s1.x, L.W[ii].x);
       L.W[ii].x = fma(-t.y, s1.y, L.W[ii].x);
       L.W[ii].y = fma(t.x, s1.y, L.W[ii].y);
       L.W[ii].y = fma(t.y, s1.x, L.W[ii].y);
+      t = cmul(t, L.r[ii]);
     } else {
       L.W[ii].x += t.x;
       L.W[ii].y += t.y;
@@ -183,9 +200,9 @@ __device__ __forceinline__ void grad_term(GradLane<M>& L, double st, double2& sb
   sb.y = fma(os.y, suf[0].x, sb.y);
 }
 
-// r += s * v (own rows, values already loaded)
-template <int M>
-__device__ __forceinline__ void grad_apply(GradLane<M>& L, double s, const double2 (&v)[M]) {
+// r += s * v (own rows, values already in registers)
+template <int M, int H>
+__device__ __forceinline__ void grad_apply(GradLane<M, H>& L, double s, const double2 (&v)[M]) {
 #pragma unroll
   for (int ii = 0; ii < M; ++ii) {
     L.r[ii].x = fma(s, v[ii].x, L.r[ii].x);
@@ -193,15 +210,9 @@ __device__ __forceinline__ void grad_apply(GradLane<M>& L, double s, const doubl
   }
 }
 
-template <int M>
-__device__ __forceinline__ void grad_load(double2 (&v)[M], const double2* col) {
-#pragma unroll
-  for (int ii = 0; ii < M; ++ii) v[ii] = col[ii];
-}
-
 // r += s * column (own rows, from LDS)
-template <int M>
-__device__ __forceinline__ void grad_update(GradLane<M>& L, double s, const double2* col) {
+template <int M, int H>
+__device__ __forceinline__ void grad_update(GradLane<M, H>& L, double s, const double2* col) {
 #pragma unroll
   for (int ii = 0; ii < M; ++ii) {
     const double2 v = col[ii];
@@ -210,19 +221,20 @@ __device__ __forceinline__ void grad_update(GradLane<M>& L, double s, const doub
   }
 }
 
-template <int M>
-__global__ __launch_bounds__(256, GradShape<M>::WAVES) void k_grad(GradArgs a) {
-  using GS = GradShape<M>;
-  constexpr int K = GS::K, U = GS::U, ROWS = GS::ROWS;
+template <int M, int H>
+__global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs a) {
+  using GS = GradShape<M, H>;
+  constexpr int K = GS::K, ROWS = GS::ROWS, NG = GS::NG;
   extern __shared__ double lds[];
-  double2* tab = reinterpret_cast<double2*>(lds);               // n * ROWS complex
-  double* stage_all = lds + 2 * (size_t)a.n * ROWS;               // 4 waves * 64 * SS complex
+  double2* tab = reinterpret_cast<double2*>(lds);  // n * ROWS complex
+  double* stage_all = lds + 2 * (size_t)a.n * ROWS;  // 4 waves * 64 * SS complex
   __shared__ int64_t s_unit;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int sig = lane & 3, grp = lane >> 2;
-  double* stage = stage_all + wave * 2 * 64 * Stage<M>::SS;
+  const int sig = lane % H, grp = lane / H;
+  double* stage = stage_all + wave * 2 * 64 * GS::SS;
   const int n = a.n, c = a.c, nb = n - 1;
   const int row0 = sig * M;
+  const bool out_lane = lane < 2 * ROWS;
   for (;;) {
     if (threadIdx.x == 0) s_unit = (int64_t)atomicAdd(a.counter, 1u);
     __syncthreads();
@@ -235,9 +247,9 @@ __global__ __launch_bounds__(256, GradShape<M>::WAVES) void k_grad(GradArgs a) {
     const int64_t slot = u * 4 + wave;
     double* ghat = reinterpret_cast<double*>(a.ghat + (size_t)slot * n * ROWS);
     // each lane zeroes the accumulator entries it will own
-    if (lane < 8 * M)
+    if (out_lane)
       for (int j = 0; j < n; ++j) ghat[j * 2 * ROWS + lane] = 0.0;
-    GradLane<M> L;
+    GradLane<M, H> L;
 #pragma unroll
     for (int b = 0; b < K; ++b)
 #pragma unroll
@@ -252,71 +264,73 @@ __global__ __launch_bounds__(256, GradShape<M>::WAVES) void k_grad(GradArgs a) {
     const int64_t sb0 = a.nsuper * sl / a.s_per, sb1 = a.nsuper * (sl + 1) / a.s_per;
     const uint64_t nchunks = (uint64_t)1 << (nb - c);
     for (int64_t sc = sb0 + wave; sc < sb1; sc += 4) {
-      const uint64_t chunk = ((uint64_t)sc << 4) + grp;
+      const uint64_t chunk = (uint64_t)sc * NG + grp;
       const uint64_t k0 = chunk << c;
-      // quads past the last chunk (tiny n) walk a copy but add nothing
+      // groups past the last chunk (tiny n) walk a copy but add nothing
       const double act = chunk < nchunks ? 1.0 : 0.0;
       // seed own rows: r_i = a_i0 + sum_{j>=1} delta_j a_ij (delta_j a_ij = (-delta_j/2) T[j])
       const uint64_t g0 = k0 ^ (k0 >> 1);
 #pragma unroll
       for (int ii = 0; ii < M; ++ii) L.r[ii] = tab[row0 + ii];
 #pragma unroll 1
-      for (int j = 1; j < n; ++j) grad_update<M>(L, ((g0 >> (j - 1)) & 1) ? 0.5 : -0.5, tab + j * ROWS + row0);
+      for (int j = 1; j < n; ++j) grad_update<M, H>(L, ((g0 >> (j - 1)) & 1) ? 0.5 : -0.5, tab + j * ROWS + row0);
 #pragma unroll
       for (int ii = 0; ii < M; ++ii) {
         if (row0 + ii >= n) L.r[ii] = make_double2(1.0, 0.0);  // padding rows
         L.W[ii] = make_double2(0.0, 0.0);
       }
       double2 sb = make_double2(0.0, 0.0);
-      grad_term<M>(L, act, sb);  // offset 0 (k0 even)
-      const uint32_t nblk = 1u << (c - K);
-      for (uint32_t m = 0; m < nblk; ++m) {
-        const uint32_t tb = m << K;
-        static_for<1, U>([&](auto scst) {
-          constexpr int s = decltype(scst)::value;
-          constexpr int b = __builtin_ctz(s);
-          // "set" <=> the new Gray bit is 1 <=> delta_{b+1} becomes -1
-          double sgu;
-          if constexpr (b + 1 < K) {
-            sgu = (((s >> (b + 1)) & 1) == 0) ? 1.0 : -1.0;
-          } else {
-            const uint64_t k = k0 + tb + s;
-            sgu = ((k >> (b + 1)) & 1) ? -1.0 : 1.0;
-          }
-          // summation by parts with W through t-1: -2 delta_new W = 2 sgu W
+      // The step to offset t flips Gray bit b = ctz(t); its new value is set
+      // iff bit b+1 of k = k0 + t is clear: from t for b+1 < c, from the
+      // chunk parity at t = L/2.
+      const double sg_half = ((k0 >> c) & 1) ? -1.0 : 1.0;
+      const uint32_t len = 1u << c;
+      for (uint32_t t = 0; t < len; ++t) {
+        if (t != 0) {
+          const int b = __builtin_ctz(t);
+          const double sgu = (b + 1 < c) ? (((t >> (b + 1)) & 1) ? -1.0 : 1.0) : sg_half;
+          if (b < K) {
+            static_for<0, K>([&](auto bc) {
+              constexpr int bb = decltype(bc)::value;
+              if (b == bb) {
+                // a distinct marker per column keeps the branches from being
+                // merged into one dynamically indexed (stack) access
+                asm volatile("; stored column %0" ::"n"(bb));
+                // summation by parts with W through t-1: -2 delta_new W = 2 sgu W
 #pragma unroll
-          for (int ii = 0; ii < M; ++ii) {
-            L.G[b][ii].x = fma(2.0 * sgu, L.W[ii].x, L.G[b][ii].x);
-            L.G[b][ii].y = fma(2.0 * sgu, L.W[ii].y, L.G[b][ii].y);
-          }
-          grad_apply<M>(L, sgu, L.colK[b]);
-          grad_term<M>(L, (s & 1) ? -act : act, sb);
-          __builtin_amdgcn_sched_barrier(0);
-        });
-        if (m + 1 < nblk) {
-          const int b = K + __builtin_ctz(m + 1);
-          const uint64_t k = k0 + tb + U;
-          const double sgu = ((k >> (b + 1)) & 1) ? -1.0 : 1.0;
-          if (b < K + GS::R) {
-            const double qs = quad_sum<M>(L.W, 2.0 * sgu, stage);
-#pragma unroll
-            for (int q = 0; q < GS::R; ++q)
-              if (b == K + q) bacc[q] += qs;
+                for (int ii = 0; ii < M; ++ii) {
+                  L.G[bb][ii].x = fma(2.0 * sgu, L.W[ii].x, L.G[bb][ii].x);
+                  L.G[bb][ii].y = fma(2.0 * sgu, L.W[ii].y, L.G[bb][ii].y);
+                }
+                grad_apply<M, H>(L, sgu, L.colK[bb]);
+              }
+            });
           } else {
-            quad_sum_add<M>(L.W, 2.0 * sgu, stage, ghat + (size_t)(b + 1) * 2 * ROWS);
+            if (b < K + GS::R) {
+              const double qs = group_sum<M, H>(L.W, 2.0 * sgu, stage);
+              static_for<0, GS::R>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                if (b == K + q) {
+                  asm volatile("; boundary column %0" ::"n"(q));
+                  bacc[q] += qs;
+                }
+              });
+            } else {
+              group_sum_add<M, H>(L.W, 2.0 * sgu, stage, ghat + (size_t)(b + 1) * 2 * ROWS);
+            }
+            grad_update<M, H>(L, sgu, tab + (b + 1) * ROWS + row0);
           }
-          grad_update<M>(L, sgu, tab + (b + 1) * ROWS + row0);
-          grad_term<M>(L, act, sb);
         }
-        flush(acc, sb, a.plain != 0, sig == 0);
+        grad_term<M, H>(L, (t & 1) ? -act : act, sb);
+        if ((t & (GRAD_FLUSH - 1)) == GRAD_FLUSH - 1 || t + 1 == len) flush(acc, sb, a.plain != 0, sig == 0);
       }
       // boundary terms delta_j(last) W(last) for every column
       const uint64_t kl = k0 + ((uint64_t)1 << c) - 1;
       const uint64_t gl = kl ^ (kl >> 1);
-      quad_sum_add<M>(L.W, 1.0, stage, ghat);  // column 0: delta_0 = +1
+      group_sum_add<M, H>(L.W, 1.0, stage, ghat);  // column 0: delta_0 = +1
 #pragma unroll 1
       for (int j = K + 1; j < n; ++j)
-        quad_sum_add<M>(L.W, ((gl >> (j - 1)) & 1) ? -1.0 : 1.0, stage, ghat + (size_t)j * 2 * ROWS);
+        group_sum_add<M, H>(L.W, ((gl >> (j - 1)) & 1) ? -1.0 : 1.0, stage, ghat + (size_t)j * 2 * ROWS);
 #pragma unroll
       for (int b = 0; b < K; ++b) {
         const double dl = ((gl >> b) & 1) ? -1.0 : 1.0;
@@ -328,14 +342,14 @@ __global__ __launch_bounds__(256, GradShape<M>::WAVES) void k_grad(GradArgs a) {
       }
     }
     // register-held boundary columns and stored columns into the accumulator
-    if (lane < 8 * M) {
+    if (out_lane) {
 #pragma unroll
       for (int q = 0; q < GS::R; ++q)
         if (K + q + 1 < n) ghat[(size_t)(K + q + 1) * 2 * ROWS + lane] += bacc[q];
     }
 #pragma unroll
     for (int b = 0; b < K; ++b)
-      if (b + 1 < n) quad_sum_add<M>(L.G[b], 1.0, stage, ghat + (size_t)(b + 1) * 2 * ROWS);
+      if (b + 1 < n) group_sum_add<M, H>(L.G[b], 1.0, stage, ghat + (size_t)(b + 1) * 2 * ROWS);
     if (sig != 0) acc = dd2{0.0, 0.0, 0.0, 0.0};
     acc = wave_reduce(acc, a.plain != 0);
     if (lane == 0) a.fparts[slot] = make_double4(acc.hr, acc.lr, acc.hi, acc.li);
@@ -413,26 +427,37 @@ __global__ void k_grad_n1(const double2* __restrict__ a, int64_t batch, const do
 
 __global__ void k_reset1(uint32_t* c) { *c = 0; }
 
-template <int M>
-static const void* grad_kernel() {
-  return (const void*)&k_grad<M>;
+// Layout of one gradient sweep: lanes per term, rows per lane, its kernel.
+struct GradLayout {
+  int H, M, K;
+  const void* kern;
+};
+
+template <int M, int H>
+static GradLayout layout() {
+  return GradLayout{H, M, GradShape<M, H>::K, (const void*)&k_grad<M, H>};
 }
 
-static const void* grad_kernel_for(int m) {
-  switch (m) {
-    case 1: return grad_kernel<1>();
-    case 2: return grad_kernel<2>();
-    case 3: return grad_kernel<3>();
-    case 4: return grad_kernel<4>();
-    case 5: return grad_kernel<5>();
-    case 6: return grad_kernel<6>();
-    case 7: return grad_kernel<7>();
-    case 8: return grad_kernel<8>();
+static GradLayout grad_layout(int n) {
+  if (n >= PH_GRAD_H8_MIN) {
+    switch ((n + 7) / 8) {
+      case 2: return layout<2, 8>();
+      case 3: return layout<3, 8>();
+      case 4: return layout<4, 8>();
+    }
   }
-  return nullptr;
+  switch ((n + 3) / 4) {
+    case 1: return layout<1, 4>();
+    case 2: return layout<2, 4>();
+    case 3: return layout<3, 4>();
+    case 4: return layout<4, 4>();
+    case 5: return layout<5, 4>();
+    case 6: return layout<6, 4>();
+    case 7: return layout<7, 4>();
+    case 8: return layout<8, 4>();
+  }
+  return GradLayout{0, 0, 0, nullptr};
 }
-
-static int grad_K(int m) { return PH_GRAD_K(m); }
 
 // Enqueue the gradient of `batch` n x n matrices (device pointers).
 int perm_grad_launch(const double2* A, int n, int64_t batch, const double2* gout, double2* pout, double2* grad,
@@ -445,14 +470,15 @@ int perm_grad_launch(const double2* A, int n, int64_t batch, const double2* gout
     e = hipGetLastError();
     return e == hipSuccess ? PH_OK : hip_fail(e, "grad launch");
   }
-  const int M = (n + 3) / 4, K = grad_K(M), rows = 4 * M, nb = n - 1;
+  const GradLayout lay = grad_layout(n);
+  if (!lay.kern) return fail(PH_ERANGE, "no gradient kernel for n=%d", n);
+  const int K = lay.K, rows = lay.H * lay.M, ng = 64 / lay.H, nb = n - 1;
   int c = o.chunk_log2 > 0 ? o.chunk_log2 : std::min(10, nb - 4);
   c = std::max(K, std::min(c, nb));
-  const int64_t nsuper = (int64_t)((((uint64_t)1 << (nb - c)) + 15) / 16);
-  const void* kern = grad_kernel_for(M);
-  const size_t lds = (size_t)n * rows * sizeof(double2) + 4 * 64 * (size_t)(M | 1) * sizeof(double2);
+  const int64_t nsuper = (int64_t)((((uint64_t)1 << (nb - c)) + ng - 1) / ng);
+  const size_t lds = (size_t)n * rows * sizeof(double2) + 4 * 64 * (size_t)(lay.M | 1) * sizeof(double2);
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lay.kern, 256, lds);
   if (e != hipSuccess) return hip_fail(e, "occupancy");
   per_cu = std::max(1, per_cu);
   if (o.waves > 0) per_cu = std::min(per_cu, o.waves);
@@ -487,7 +513,7 @@ int perm_grad_launch(const double2* A, int n, int64_t batch, const double2* gout
                      const_cast<double2*>(ga.tabs));
   const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(blocks_full, units));
   void* args[] = {&ga};
-  e = hipLaunchKernel(kern, dim3((unsigned)grid), dim3(256), args, lds, st);
+  e = hipLaunchKernel(lay.kern, dim3((unsigned)grid), dim3(256), args, lds, st);
   if (e != hipSuccess) return hip_fail(e, "grad sweep launch");
   hipLaunchKernelGGL(k_grad_finalize, dim3((unsigned)batch), dim3(256), 0, st, ga.ghat, ga.fparts, n, rows,
                      (int)s_per, ga.plain, gout, pout, grad);
