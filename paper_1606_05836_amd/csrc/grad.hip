@@ -29,9 +29,11 @@
 //     global memory.  Every address of that accumulator is read and written by
 //     one fixed lane only, so program order is the only ordering needed.
 //
-// The loop body holds one copy of the term code: the flipped bit ctz(t) is
-// the same on every lane, so the choice between a register-held column and a
-// boundary column is a scalar branch.
+// The loop takes the terms in pairs (t, t+1), t even, with one copy of the
+// code for each: the step into t+1 always flips Gray bit 0, and the step into
+// t flips bit ctz(t), the same on every lane, so the choice between a
+// register-held column and a boundary column is a scalar branch taken once
+// per pair.
 //
 // The forward permanent comes out of the same sweep (prod of all rows).
 // All sums are in a fixed order, so results are bitwise reproducible.
@@ -285,18 +287,18 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
       // chunk parity at t = L/2.
       const double sg_half = ((k0 >> c) & 1) ? -1.0 : 1.0;
       const uint32_t len = 1u << c;
-      for (uint32_t t = 0; t < len; ++t) {
+      // Terms in pairs (t, t+1), t even: the step into t+1 always flips bit 0
+      // (straight-line code); the step into t flips bit ctz(t) >= 1.
+      const double sg0_half = c == 1 ? sg_half : 0.0;
+      for (uint32_t t = 0; t < len; t += 2) {
         if (t != 0) {
           const int b = __builtin_ctz(t);
           const double sgu = (b + 1 < c) ? (((t >> (b + 1)) & 1) ? -1.0 : 1.0) : sg_half;
           if (b < K) {
-            static_for<0, K>([&](auto bc) {
+            static_for<1, K>([&](auto bc) {
               constexpr int bb = decltype(bc)::value;
               if (b == bb) {
-                // a distinct marker per column keeps the branches from being
-                // merged into one dynamically indexed (stack) access
                 asm volatile("; stored column %0" ::"n"(bb));
-                // summation by parts with W through t-1: -2 delta_new W = 2 sgu W
 #pragma unroll
                 for (int ii = 0; ii < M; ++ii) {
                   L.G[bb][ii].x = fma(2.0 * sgu, L.W[ii].x, L.G[bb][ii].x);
@@ -321,8 +323,18 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
             grad_update<M, H>(L, sgu, tab + (b + 1) * ROWS + row0);
           }
         }
-        grad_term<M, H>(L, (t & 1) ? -act : act, sb);
-        if ((t & (GRAD_FLUSH - 1)) == GRAD_FLUSH - 1 || t + 1 == len) flush(acc, sb, a.plain != 0, sig == 0);
+        grad_term<M, H>(L, act, sb);
+        {
+          const double sgu = c > 1 ? (((t >> 1) & 1) ? -1.0 : 1.0) : sg0_half;
+#pragma unroll
+          for (int ii = 0; ii < M; ++ii) {
+            L.G[0][ii].x = fma(2.0 * sgu, L.W[ii].x, L.G[0][ii].x);
+            L.G[0][ii].y = fma(2.0 * sgu, L.W[ii].y, L.G[0][ii].y);
+          }
+          grad_apply<M, H>(L, sgu, L.colK[0]);
+        }
+        grad_term<M, H>(L, -act, sb);
+        if (((t + 2) & (GRAD_FLUSH - 1)) == 0 || t + 2 == len) flush(acc, sb, a.plain != 0, sig == 0);
       }
       // boundary terms delta_j(last) W(last) for every column
       const uint64_t kl = k0 + ((uint64_t)1 << c) - 1;
@@ -452,9 +464,15 @@ static GradLayout grad_layout(int n) {
     case 3: return layout<3, 4>();
     case 4: return layout<4, 4>();
     case 5: return layout<5, 4>();
+#if PH_GRAD_H8_MIN > 21
     case 6: return layout<6, 4>();
+#endif
+#if PH_GRAD_H8_MIN > 25
     case 7: return layout<7, 4>();
+#endif
+#if PH_GRAD_H8_MIN > 29
     case 8: return layout<8, 4>();
+#endif
   }
   return GradLayout{0, 0, 0, nullptr};
 }
