@@ -75,9 +75,13 @@ constexpr int DPP_QUAD_XOR1 = 0xB1, DPP_QUAD_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x14
 #endif
 // smallest n that uses H = 8 lanes per term
 #ifndef PH_GRAD_H8_MIN
-#define PH_GRAD_H8_MIN 21
+#define PH_GRAD_H8_MIN 9
 #endif
 
+// log2 of the terms per loop iteration (bits below it flip without a branch)
+#ifndef PH_GRAD_LOGP
+#define PH_GRAD_LOGP(M, H) ((M) == 3 && (H) == 8 ? 2 : 1)
+#endif
 // terms summed in plain binary64 before each double-double accumulation
 constexpr uint32_t GRAD_FLUSH = 16;
 
@@ -90,6 +94,8 @@ struct GradShape {
   // their group sums in registers of the owning lane
   static constexpr int R = 4;
   static constexpr int WAVES = PH_GRAD_WAVES(M, H);
+  // terms per loop iteration: 2^LOGP (LOGP <= K)
+  static constexpr int LOGP = PH_GRAD_LOGP(M, H) < K ? PH_GRAD_LOGP(M, H) : K;
   // LDS staging: lane l writes its M complex values at complex offset l * SS,
   // SS = M rounded up to odd, so the 16-byte writes of eight consecutive
   // lanes cover all 32 banks once and the reads are conflict-free
@@ -287,15 +293,17 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
       // chunk parity at t = L/2.
       const double sg_half = ((k0 >> c) & 1) ? -1.0 : 1.0;
       const uint32_t len = 1u << c;
-      // Terms in pairs (t, t+1), t even: the step into t+1 always flips bit 0
-      // (straight-line code); the step into t flips bit ctz(t) >= 1.
-      const double sg0_half = c == 1 ? sg_half : 0.0;
-      for (uint32_t t = 0; t < len; t += 2) {
+      // Terms in runs of P = 2^LOGP: the steps inside a run flip bits below
+      // LOGP (straight-line code, columns in registers); the step into the
+      // run's first term flips bit ctz(t) >= LOGP.
+      constexpr int LOGP = GS::LOGP;
+      constexpr uint32_t P = 1u << LOGP;
+      for (uint32_t t = 0; t < len; t += P) {
         if (t != 0) {
           const int b = __builtin_ctz(t);
           const double sgu = (b + 1 < c) ? (((t >> (b + 1)) & 1) ? -1.0 : 1.0) : sg_half;
           if (b < K) {
-            static_for<1, K>([&](auto bc) {
+            static_for<LOGP, K>([&](auto bc) {
               constexpr int bb = decltype(bc)::value;
               if (b == bb) {
                 asm volatile("; stored column %0" ::"n"(bb));
@@ -323,18 +331,23 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
             grad_update<M, H>(L, sgu, tab + (b + 1) * ROWS + row0);
           }
         }
-        grad_term<M, H>(L, act, sb);
-        {
-          const double sgu = c > 1 ? (((t >> 1) & 1) ? -1.0 : 1.0) : sg0_half;
+        // the new value of bit LOGP-1 within the run comes from bit LOGP of t
+        const double sg_top = LOGP < c ? (((t >> LOGP) & 1) ? -1.0 : 1.0) : sg_half;
+        static_for<0, P>([&](auto sc) {
+          constexpr uint32_t so = decltype(sc)::value;
+          if constexpr (so != 0) {
+            constexpr int bb = __builtin_ctz(so);
+            const double sgu = bb + 1 < LOGP ? (((so >> (bb + 1)) & 1) ? -1.0 : 1.0) : sg_top;
 #pragma unroll
-          for (int ii = 0; ii < M; ++ii) {
-            L.G[0][ii].x = fma(2.0 * sgu, L.W[ii].x, L.G[0][ii].x);
-            L.G[0][ii].y = fma(2.0 * sgu, L.W[ii].y, L.G[0][ii].y);
+            for (int ii = 0; ii < M; ++ii) {
+              L.G[bb][ii].x = fma(2.0 * sgu, L.W[ii].x, L.G[bb][ii].x);
+              L.G[bb][ii].y = fma(2.0 * sgu, L.W[ii].y, L.G[bb][ii].y);
+            }
+            grad_apply<M, H>(L, sgu, L.colK[bb]);
           }
-          grad_apply<M, H>(L, sgu, L.colK[0]);
-        }
-        grad_term<M, H>(L, -act, sb);
-        if (((t + 2) & (GRAD_FLUSH - 1)) == 0 || t + 2 == len) flush(acc, sb, a.plain != 0, sig == 0);
+          grad_term<M, H>(L, (so & 1) ? -act : act, sb);
+        });
+        if (((t + P) & (GRAD_FLUSH - 1)) == 0 || t + P == len) flush(acc, sb, a.plain != 0, sig == 0);
       }
       // boundary terms delta_j(last) W(last) for every column
       const uint64_t kl = k0 + ((uint64_t)1 << c) - 1;
@@ -457,13 +470,20 @@ static GradLayout grad_layout(int n) {
       case 3: return layout<3, 8>();
       case 4: return layout<4, 8>();
     }
+    return GradLayout{0, 0, 0, nullptr};
   }
   switch ((n + 3) / 4) {
     case 1: return layout<1, 4>();
     case 2: return layout<2, 4>();
+#if PH_GRAD_H8_MIN > 9
     case 3: return layout<3, 4>();
+#endif
+#if PH_GRAD_H8_MIN > 13
     case 4: return layout<4, 4>();
+#endif
+#if PH_GRAD_H8_MIN > 17
     case 5: return layout<5, 4>();
+#endif
 #if PH_GRAD_H8_MIN > 21
     case 6: return layout<6, 4>();
 #endif
@@ -492,7 +512,7 @@ int perm_grad_launch(const double2* A, int n, int64_t batch, const double2* gout
   if (!lay.kern) return fail(PH_ERANGE, "no gradient kernel for n=%d", n);
   const int K = lay.K, rows = lay.H * lay.M, ng = 64 / lay.H, nb = n - 1;
   int c = o.chunk_log2 > 0 ? o.chunk_log2 : std::min(10, nb - 4);
-  c = std::max(K, std::min(c, nb));
+  c = std::max(K, std::min(c, nb));  // K >= LOGP, so a chunk holds whole runs
   const int64_t nsuper = (int64_t)((((uint64_t)1 << (nb - c)) + ng - 1) / ng);
   const size_t lds = (size_t)n * rows * sizeof(double2) + 4 * 64 * (size_t)(lay.M | 1) * sizeof(double2);
   int per_cu = 0;
