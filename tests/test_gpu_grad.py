@@ -149,3 +149,29 @@ def test_larger_n_identities(ph, n):
     assert rel <= 1e-9, rel
     fwd = complex(ph.perm(cuda(a)).cpu())
     assert abs(complex(p.cpu()) - fwd) <= 1e-11 * abs(fwd)
+
+
+@pytest.mark.parametrize("n", [8, 9, 16, 17])
+def test_sampled_minors_at_layout_boundaries(ph, n):
+    # the sweep changes its lane layout with n (4 -> 8 lanes per term above 8,
+    # 2 -> 3 rows per lane above 16); exact minors on both sides
+    a = I.submatrix(I.haar(64, 300 + n), range(3, 3 + n), range(n))
+    p, g = ph.perm_grad(cuda(a))
+    m = np.conj(g.cpu().numpy())
+    rng = np.random.default_rng(n)
+    picks = [(0, 0), (n - 1, n - 1), (n // 2, 1)] + [tuple(rng.integers(0, n, 2)) for _ in range(2)]
+    for i, j in picks:
+        assert O.rel_err(complex(m[i, j]), O.minor_perm_exact(a, int(i), int(j))) <= 1e-10, (n, i, j)
+    assert O.rel_err(complex(p.cpu()), O.perm_exact(a)) <= 1e-10
+
+
+@pytest.mark.parametrize("n", [22, 24, 26, 28, 30])
+def test_sweep_permanent_against_stored_exact(ph, n):
+    # the permanent the gradient sweep produces on the way (3 and 4 rows per
+    # lane) against the oracle's stored exact value
+    a = I.config3_matrix(n)
+    ex = G.value_for("haar", f"config3_n{n}", a)
+    if ex is None:
+        pytest.skip("stored value absent")
+    p, _ = ph.perm_grad(cuda(a))
+    assert O.rel_err(complex(p.cpu()), ex) <= 1e-10
