@@ -17,6 +17,7 @@ probabilities/s and the gradient's cost.
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 40]
                        [--no-cpu] [--no-extras] [--copy-probe MiB]
        python bench.py --precision 40,44   (precision study only)
+       python bench.py --precision-allr    (the paper's all-r precision workload)
 """
 from __future__ import annotations
 
@@ -235,6 +236,54 @@ def precision(ph, dev, large):
     return {"against_exact": rows, "large_n": big}
 
 
+def _parse_r(tok: str) -> complex:
+    """'1', '0.1', '1+i', '10+10i' -> complex."""
+    if tok.endswith("i"):
+        re_, im_ = tok[:-1].split("+")
+        return complex(float(re_), float(im_) if im_ else 1.0)
+    return complex(float(tok), 0.0)
+
+
+def precision_allr(ph, dev):
+    """The paper's all-r precision workload: for every (n, r) of its error
+    tables, the relative error of BB/FG and Ryser (dd and plain outer sums)
+    against the exact r^n n! of the binary64 input, beside the errors the
+    paper prints for its own runs (tests/golden/paper_allr_relerr.txt)."""
+    import math
+    from fractions import Fraction
+
+    import torch
+
+    printed = {}
+    with open(os.path.join(ROOT, "tests", "golden", "paper_allr_relerr.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            table, n, r, rel = line.split()
+            printed[(table.split("_")[0], int(n), r)] = float(rel)
+    rows = []
+    for (n, r) in sorted({(k[1], k[2]) for k in printed}):
+        z = _parse_r(r)
+        # exact value for the binary64 entries: fl(r)^n n!
+        zr, zi = Fraction(z.real), Fraction(z.imag)
+        pr, pi = Fraction(1), Fraction(0)
+        for _ in range(n):
+            pr, pi = pr * zr - pi * zi, pr * zi + pi * zr
+        exact = complex(pr * math.factorial(n)) + 1j * float(pi * math.factorial(n))
+        a = torch.full((n, n), z, dtype=torch.complex128, device=dev)
+        row = {"n": n, "r": r}
+        for algo in ("glynn", "ryser"):
+            for accum in ("dd", "plain"):
+                v = complex(ph.perm(a, algo=algo, accum=accum).cpu())
+                row[f"{algo}_{accum}"] = abs(v - exact) / abs(exact)
+        row["paper_bbfg"] = printed.get(("bbfg", n, r))
+        row["paper_ryser"] = printed.get(("ryser", n, r))
+        rows.append(row)
+        if n % 4 == 0:
+            _log(f"all-r precision: n={n} r={r} done")
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,6 +299,8 @@ def main():
                     help="run one plain device copy of this size first (counter calibration)")
     ap.add_argument("--precision", default="", metavar="N,N",
                     help="print only the precision study, with these large sizes (e.g. 40,44)")
+    ap.add_argument("--precision-allr", action="store_true",
+                    help="print only the precision study on the paper's all-r matrices")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the sweep runs on a single "
@@ -269,6 +320,9 @@ def main():
     out = torch.empty((), dtype=torch.complex128, device=dev)
     stream = torch.cuda.current_stream(dev)
     kw = dict(accum=args.accum, chunk_log2=args.chunk_log2, waves=args.waves)
+    if args.precision_allr:
+        print(json.dumps({"precision_allr": precision_allr(ph, dev)}), flush=True)
+        return
     if args.precision:
         large = [int(x) for x in args.precision.split(",") if x.strip() and int(x) > 0]
         print(json.dumps({"precision": precision(ph, dev, large)}), flush=True)

@@ -99,11 +99,20 @@ def _need_c128_cuda(name: str, t: torch.Tensor):
 
 def perm(a: torch.Tensor, algo="glynn", accum="dd", chunk_log2: int = 0, waves: int = 0,
          out: torch.Tensor | None = None) -> torch.Tensor:
-    """Per(a) for one n x n complex128 matrix on the GPU (rows may be strided).
-    Returns a 0-dim complex128 tensor on the same device."""
+    """Per(a) for an n x n complex128 matrix on the GPU (rows may be strided):
+    a 0-dim complex128 tensor.  For a (..., n, n) tensor the permanents of all
+    matrices go through ph_perm_batched and come back with shape (...)."""
     _need_c128_cuda("a", a)
-    if a.dim() != 2 or a.shape[0] != a.shape[1]:
-        raise ValueError("a must be n x n")
+    if a.dim() < 2 or a.shape[-1] != a.shape[-2]:
+        raise ValueError("a must be (..., n, n)")
+    if a.dim() > 2:
+        if out is not None:
+            raise ValueError("out is supported for a single matrix only")
+        lead, n = a.shape[:-2], a.shape[-1]
+        flat = a.reshape(-1, n, n)
+        res = perm_batched(flat, algo, accum, chunk_log2, waves) if flat.shape[0] else \
+            torch.empty(0, dtype=torch.complex128, device=a.device)
+        return res.reshape(lead)
     n = a.shape[0]
     if n > 0 and a.stride(1) != 1:
         a = a.contiguous()

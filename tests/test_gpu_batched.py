@@ -107,3 +107,15 @@ def test_fp64_peak_microbenchmark(ph):
     gflops, mhz = ph.fp64_peak(1 << 12)
     assert gflops > 10_000  # far below the 78.6 TFLOP/s spec; a sanity floor
     assert mhz == 0 or 500 < mhz < 4000
+
+
+def test_perm_of_leading_batch_dims(ph):
+    # perm(a) with a (..., n, n) tensor goes through the batched path; the
+    # values match the oracle matrix by matrix
+    a = I.config4_batch(6, 9).reshape(2, 3, 9, 9)
+    got = ph.perm(torch.from_numpy(a).to("cuda"))
+    assert got.shape == (2, 3)
+    for i in range(2):
+        for j in range(3):
+            assert O.rel_err(complex(got[i, j]), O.perm_exact(a[i, j])) <= 1e-12
+    assert ph.perm(torch.zeros((0, 4, 4), dtype=torch.complex128, device="cuda")).shape == (0,)

@@ -144,6 +144,17 @@ def test_all_r_matrices_glynn(ph):
             assert O.rel_err(run(ph, I.all_r(n, r)), ex) <= TOL, (n, r)
 
 
+@pytest.mark.parametrize("n", [32, 36])
+def test_all_r_matrices_glynn_large_n(ph, n):
+    """The paper's all-r workload at the top of its tables: BB/FG with the
+    double-double outer sum stays within 1e-9 (the paper prints up to 5.7e-9
+    for its own BB/FG runs at n = 36); Ryser on the same inputs is what the
+    precision issue of the Supplementary analysis is about, reported by
+    bench.py --precision-allr, not asserted."""
+    for r in (1.0, 0.1, 1 + 1j):
+        assert O.rel_err(run(ph, I.all_r(n, r)), _allr_exact(n, r)) <= 1e-9, (n, r)
+
+
 def _allr_exact(n, r):
     rr = (Fraction(complex(r).real), Fraction(complex(r).imag))
     re, im = Fraction(1), Fraction(0)
