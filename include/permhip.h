@@ -53,6 +53,7 @@ typedef struct {
 
 enum { PH_GLYNN = 0, PH_RYSER = 1 };
 enum { PH_ACC_DD = 0, PH_ACC_PLAIN = 1 };
+#define PH_FLAG_UNGROUPED 1u
 
 /* Options; pass NULL for the defaults (Glynn, double-double, tuned sizes).
  *   algo        PH_GLYNN or PH_RYSER
@@ -61,7 +62,8 @@ enum { PH_ACC_DD = 0, PH_ACC_PLAIN = 1 };
  *               of its row sums; 0 = library choice.  Values outside the
  *               range the kernel supports for n are clamped.
  *   waves       wavefronts per SIMD to launch (1..8); 0 = library choice
- *   flags       reserved, must be 0 */
+ *   flags       0, or PH_FLAG_UNGROUPED (ph_boson_probs only: one full sweep
+ *               per pattern instead of the multiplicity-grouped sweeps) */
 typedef struct {
   int32_t algo;
   int32_t accum;
@@ -135,6 +137,15 @@ int ph_perm_grad(const ph_c128* A, int32_t n, int64_t batch, const ph_c128* grad
  * each photon of pattern p, likewise with repeats.  U_{S,T} has rows =
  * pattern modes and columns = input modes, both in the given order.
  * probs (device, n_patterns doubles) receives the probabilities.
+ * A pattern whose output modes repeat is evaluated through Eq. (S2) grouped by
+ * multiplicity: with output mode l holding mu_l photons, the signs of its mu_l
+ * copies enter only through their count k_l of -1 entries, so
+ *   Per = 2^-(n-1) sum_{k} prod_l C(mu_l, k_l) (-1)^{k_l} prod_i sum_l (mu_l - 2 k_l) u_{l, s_i}
+ * (one single-photon mode's sign fixed), i.e. one BB/FG sweep over the
+ * single-photon modes per choice of k for the collided ones: prod_l (mu_l + 1)
+ * / 2 terms in place of 2^(n-1).  Patterns with fewer than 5 single-photon
+ * modes, and every pattern under PH_FLAG_UNGROUPED, take one sweep of
+ * 2^(n-1) terms.  The host arrays are copied before the call returns.
  * 1 <= n <= PH_NMAX_GRAD for the gradient entry point, n <= PH_NMAX here. */
 int ph_boson_probs(const ph_c128* U, int32_t m, int64_t ldu, const int32_t* in_modes, int32_t n,
                    const int32_t* patterns, int64_t n_patterns, double* probs, const ph_opts* opt, void* stream);

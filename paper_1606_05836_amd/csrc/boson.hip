@@ -19,6 +19,7 @@
 #include <utility>
 #include <vector>
 
+#include "dd.hpp"
 #include "permhip.h"
 #include "ph_host.hpp"
 #include "ph_internal.hpp"
@@ -123,14 +124,14 @@ struct Staging {
 static std::mutex g_stage_mu;
 static std::map<std::pair<int, hipStream_t>, Staging> g_stage;
 
-// Copy `bytes` from the host pieces into device memory `dst` on `st`.
+// Copy the host pieces into device memory at base + off[q] (piece q), one
+// transfer of off[npc] bytes on `st` through the pinned staging buffer.
 struct Piece {
   const void* src;
   size_t bytes;
 };
-static int upload(hipStream_t st, void* dst, const Piece* pc, int npc) {
-  size_t bytes = 0;
-  for (int q = 0; q < npc; ++q) bytes += up256(pc[q].bytes);
+static int upload_at(hipStream_t st, void* base, const size_t* off, const Piece* pc, int npc) {
+  const size_t bytes = off[npc];
   if (bytes == 0) return PH_OK;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -156,17 +157,21 @@ static int upload(hipStream_t st, void* dst, const Piece* pc, int npc) {
     s.cap = cap;
   }
   char* h = static_cast<char*>(s.host);
-  size_t off = 0;
-  for (int q = 0; q < npc; ++q) {
-    if (pc[q].bytes) std::memcpy(h + off, pc[q].src, pc[q].bytes);
-    off += up256(pc[q].bytes);
-  }
-  e = hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, st);
+  for (int q = 0; q < npc; ++q)
+    if (pc[q].bytes) std::memcpy(h + off[q], pc[q].src, pc[q].bytes);
+  e = hipMemcpyAsync(base, h, bytes, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return hip_fail(e, "mode upload");
   e = hipEventRecord(s.ev, st);
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
   s.pending = true;
   return PH_OK;
+}
+
+// Pieces packed back to back at 256-byte boundaries.
+static int upload(hipStream_t st, void* dst, const Piece* pc, int npc) {
+  std::vector<size_t> off(npc + 1, 0);
+  for (int q = 0; q < npc; ++q) off[q + 1] = off[q] + up256(pc[q].bytes);
+  return upload_at(st, dst, off.data(), pc, npc);
 }
 
 // Device buffers of one boson call, in workspace slot 1 of the stream (the
@@ -226,6 +231,213 @@ static int boson_setup(hipStream_t st, const ph_c128* U, int32_t m, int64_t ldu,
   return PH_OK;
 }
 
+
+// ------------------------------------------------ multiplicity-grouped sweeps
+//
+// Per(U_{S,T}) = Per(B) with B = U_{S,T}^T (rows: input photons, columns:
+// output photons).  The columns of B that belong to one output mode l are
+// equal (mu_l copies).  In Eq. (S2) the signs of those copies enter the row
+// sums as (mu_l - 2 k_l) b_l and the sign product as (-1)^{k_l}, with k_l
+// their number of -1 entries, C(mu_l, k_l) ways each.  With the sign of one
+// single-photon mode l0 fixed:
+//   Per = 2^-(n-1) sum_{k over collided modes} w(k) G(k),
+//   w(k) = prod_l C(mu_l, k_l) (-1)^{k_l},
+//   G(k) = BB/FG sum over the single-photon modes of the n x n1 table whose
+//          first column is b_l0 + sum_l (mu_l - 2 k_l) b_l.
+// Each (pattern, k) is one sweep of 2^(n1-1) terms of the batched kernels.
+
+// Sweep tables: column 0 = U[mode0, S_i] + sum_c coef_c U[coll_c, S_i],
+// column j >= 1 = -2 U[mode_j, S_i]; column-major, n rows per column.
+__global__ void k_boson_vtab(const double2* __restrict__ u, int64_t ldu, const int32_t* __restrict__ in_modes, int n,
+                             const int32_t* __restrict__ vcol, const int32_t* __restrict__ vncols,
+                             const int32_t* __restrict__ vcoef, const int32_t* __restrict__ vncoef,
+                             const int32_t* __restrict__ colmodes, const int32_t* __restrict__ collmodes,
+                             const double* __restrict__ coefs, const int64_t* __restrict__ tab_off,
+                             double2* __restrict__ tabs) {
+  const int64_t v = blockIdx.x;
+  const int ncols = vncols[v];
+  const int32_t* cm = colmodes + vcol[v];
+  const int c0 = vcoef[v], nc = vncoef[v];
+  double2* t = tabs + tab_off[v];
+  for (int e = threadIdx.x; e < n * ncols; e += blockDim.x) {
+    const int j = e / n, i = e % n;
+    const int64_t s = in_modes[i];
+    double2 val = u[(int64_t)cm[j] * ldu + s];
+    if (j == 0) {
+      for (int q = 0; q < nc; ++q) {
+        const double w = coefs[c0 + q];
+        const double2 b = u[(int64_t)collmodes[c0 + q] * ldu + s];
+        val.x = fma(w, b.x, val.x);
+        val.y = fma(w, b.y, val.y);
+      }
+    } else {
+      val = make_double2(-2.0 * val.x, -2.0 * val.y);
+    }
+    t[(int64_t)j * n + i] = val;
+  }
+}
+
+// perms[p] = sum over the pattern's sweeps, in order, of w_v * vout[v]
+__global__ void k_boson_combine(const double2* __restrict__ vout, const double* __restrict__ w,
+                                const int32_t* __restrict__ pv, int64_t npat, int plain, double2* __restrict__ perms) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= npat) return;
+  dd2 s = {0.0, 0.0, 0.0, 0.0};
+  for (int32_t v = pv[p]; v < pv[p + 1]; ++v) {
+    const double2 x = vout[v];
+    if (plain) {
+      s.hr = fma(w[v], x.x, s.hr);
+      s.hi = fma(w[v], x.y, s.hi);
+    } else {
+      // w is a small integer: w * x is one rounding, accumulated compensated
+      dd_accumulate(s, w[v] * x.x, w[v] * x.y);
+    }
+  }
+  perms[p] = make_double2(s.hr + s.lr, s.hi + s.li);
+}
+
+// Host description of the sweeps of a call.
+struct Sweeps {
+  std::vector<int32_t> vcol, vncols, vcoef, vncoef;  // per sweep
+  std::vector<double> w;                            // per sweep
+  std::vector<int32_t> colmodes, collmodes;
+  std::vector<double> coefs;
+  std::vector<int32_t> pv;  // per pattern: first sweep (npat + 1 entries)
+};
+
+// Limits: single-photon modes a grouped pattern needs (the sweep kernels walk
+// at least 4 Gray bits), sweeps per pattern, sweeps per call.
+constexpr int GROUP_MIN_SINGLES = 5;
+constexpr int64_t GROUP_MAX_PER_PATTERN = 4096;
+constexpr int64_t GROUP_MAX_SWEEPS = (int64_t)1 << 17;
+
+static void plan_sweeps(const int32_t* patterns, int n, int64_t npat, bool ungrouped, Sweeps* sw) {
+  sw->pv.assign(npat + 1, 0);
+  int64_t budget = GROUP_MAX_SWEEPS;
+  std::vector<std::pair<int32_t, int>> cls;  // (mode, photons), first-appearance order
+  for (int64_t p = 0; p < npat; ++p) {
+    const int32_t* t = patterns + p * n;
+    sw->pv[p] = (int32_t)sw->w.size();
+    cls.clear();
+    for (int i = 0; i < n; ++i) {
+      bool found = false;
+      for (auto& c : cls)
+        if (c.first == t[i]) {
+          ++c.second;
+          found = true;
+          break;
+        }
+      if (!found) cls.emplace_back(t[i], 1);
+    }
+    int singles = 0;
+    int64_t combos = 1;
+    for (auto& c : cls) {
+      if (c.second == 1) ++singles;
+      else combos *= c.second + 1;
+      if (combos > GROUP_MAX_PER_PATTERN) break;
+    }
+    const bool group = !ungrouped && singles >= GROUP_MIN_SINGLES && combos > 1 &&
+                       combos <= GROUP_MAX_PER_PATTERN && combos <= budget;
+    if (!group) {
+      // one sweep over all n columns (repeats included), weight 1
+      sw->vcol.push_back((int32_t)sw->colmodes.size());
+      sw->colmodes.insert(sw->colmodes.end(), t, t + n);
+      sw->vncols.push_back(n);
+      sw->vcoef.push_back((int32_t)sw->coefs.size());
+      sw->vncoef.push_back(0);
+      sw->w.push_back(1.0);
+      continue;
+    }
+    budget -= combos;
+    const int32_t col_off = (int32_t)sw->colmodes.size();
+    for (auto& c : cls)
+      if (c.second == 1) sw->colmodes.push_back(c.first);
+    std::vector<std::pair<int32_t, int>> coll;
+    for (auto& c : cls)
+      if (c.second > 1) coll.push_back(c);
+    std::vector<int> k(coll.size(), 0);
+    for (int64_t q = 0; q < combos; ++q) {
+      // k in mixed radix (first collided mode fastest)
+      int64_t r = q;
+      double w = 1.0;
+      sw->vcoef.push_back((int32_t)sw->coefs.size());
+      sw->vncoef.push_back((int32_t)coll.size());
+      for (size_t l = 0; l < coll.size(); ++l) {
+        const int mu = coll[l].second;
+        k[l] = (int)(r % (mu + 1));
+        r /= mu + 1;
+        double binom = 1.0;
+        for (int z = 0; z < k[l]; ++z) binom = binom * (mu - z) / (z + 1);
+        w *= (k[l] & 1) ? -binom : binom;
+        sw->collmodes.push_back(coll[l].first);
+        sw->coefs.push_back((double)(mu - 2 * k[l]));
+      }
+      sw->vcol.push_back(col_off);
+      sw->vncols.push_back(singles);
+      sw->w.push_back(w);
+    }
+  }
+  sw->pv[npat] = (int32_t)sw->w.size();
+}
+
+// Eq. (1) permanents of all patterns through the grouped sweeps into perms
+// (device, npat complex).  in_dev: the input modes already on the device.
+static int boson_perms_grouped(hipStream_t st, const ph_c128* U, int64_t ldu, const int32_t* in_modes, int n,
+                               const int32_t* patterns, int64_t npat, const Opts& o, double2* perms) {
+  Sweeps sw;
+  plan_sweeps(patterns, n, npat, o.ungrouped, &sw);
+  const int64_t V = (int64_t)sw.w.size();
+  std::vector<int32_t> ns(V, n);
+  // device layout in workspace slot 2: in_modes | vcol | vncols | vcoef | vncoef |
+  // colmodes | collmodes | pv | coefs | w | tab_off | vout
+  auto one = [](size_t x) { return std::max<size_t>(x, 1); };
+  const size_t sz[12] = {one(n) * 4,        one(V) * 4,          one(V) * 4,
+                         one(V) * 4,        one(V) * 4,          one(sw.colmodes.size()) * 4,
+                         one(sw.collmodes.size()) * 4, one(npat + 1) * 4, one(sw.coefs.size()) * 8,
+                         one(V) * 8,        one(V) * 8,          one(V) * 16};
+  size_t off[13];
+  off[0] = 0;
+  for (int q = 0; q < 12; ++q) off[q + 1] = off[q] + up256(sz[q]);
+  void* ws = nullptr;
+  int rc = workspace_slot(st, off[12], 2, &ws);
+  if (rc) return rc;
+  char* d = static_cast<char*>(ws);
+  auto I32 = [&](int q) { return reinterpret_cast<int32_t*>(d + off[q]); };
+  double* d_coefs = reinterpret_cast<double*>(d + off[8]);
+  double* d_w = reinterpret_cast<double*>(d + off[9]);
+  int64_t* d_taboff = reinterpret_cast<int64_t*>(d + off[10]);
+  double2* vout = reinterpret_cast<double2*>(d + off[11]);
+  auto fill = [&](PlanImpl* p) -> int {
+    const std::vector<int64_t>& toff = plan_table_offsets(p);
+    const Piece pc[11] = {{in_modes, (size_t)n * 4},
+                          {sw.vcol.data(), (size_t)V * 4},
+                          {sw.vncols.data(), (size_t)V * 4},
+                          {sw.vcoef.data(), (size_t)V * 4},
+                          {sw.vncoef.data(), (size_t)V * 4},
+                          {sw.colmodes.data(), sw.colmodes.size() * 4},
+                          {sw.collmodes.data(), sw.collmodes.size() * 4},
+                          {sw.pv.data(), (size_t)(npat + 1) * 4},
+                          {sw.coefs.data(), sw.coefs.size() * 8},
+                          {sw.w.data(), (size_t)V * 8},
+                          {toff.data(), (size_t)V * 8}};
+    int r = upload_at(st, d, off, pc, 11);
+    if (r) return r;
+    hipLaunchKernelGGL(k_boson_vtab, dim3((unsigned)V), dim3(256), 0, st, reinterpret_cast<const double2*>(U), ldu,
+                       I32(0), n, I32(1), I32(2), I32(3), I32(4), I32(5), I32(6), d_coefs, d_taboff,
+                       plan_tables_base(p));
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? PH_OK : hip_fail(e, "boson table launch");
+  };
+  Opts og = o;
+  og.algo = PH_GLYNN;
+  rc = plan_ext_run(ns.data(), sw.vncols.data(), V, og, st, fill, vout);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_boson_combine, dim3((unsigned)((npat + 255) / 256)), dim3(256), 0, st, vout, d_w, I32(7),
+                     npat, o.plain ? 1 : 0, perms);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? PH_OK : hip_fail(e, "boson combine launch");
+}
+
 }  // namespace ph
 
 using namespace ph;
@@ -243,9 +455,13 @@ extern "C" int ph_boson_probs(const ph_c128* U, int32_t m, int64_t ldu, const in
   hipStream_t st = (hipStream_t)stream;
   BosonBufs b;
   if ((rc = boson_setup(st, U, m, ldu, in_modes, n, patterns, n_patterns, false, &b))) return rc;
-  std::vector<int32_t> ns(n_patterns, n);
-  rc = ph_perm_batched(reinterpret_cast<const ph_c128*>(b.a), nullptr, ns.data(), n_patterns,
-                       reinterpret_cast<ph_c128*>(b.perms), opt, stream);
+  if (n >= GROUP_MIN_SINGLES + 1 && o.algo == PH_GLYNN) {
+    rc = boson_perms_grouped(st, U, ldu, in_modes, n, patterns, n_patterns, o, b.perms);
+  } else {
+    std::vector<int32_t> ns(n_patterns, n);
+    rc = ph_perm_batched(reinterpret_cast<const ph_c128*>(b.a), nullptr, ns.data(), n_patterns,
+                         reinterpret_cast<ph_c128*>(b.perms), opt, stream);
+  }
   if (rc) return rc;
   hipLaunchKernelGGL(k_boson_normalize, dim3((unsigned)((n_patterns + 255) / 256)), dim3(256), 0, st, b.perms,
                      b.d_in, b.d_pat, n, n_patterns, (const double*)nullptr, probs, (double2*)nullptr);

@@ -3,6 +3,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
+#include <vector>
+
 #include "permhip.h"
 
 namespace ph {
@@ -12,6 +15,7 @@ struct Opts {
   bool plain = false;  // plain binary64 outer sum instead of double-double
   int chunk_log2 = 0;  // 0 = library choice
   int waves = 0;       // waves per SIMD, 0 = occupancy limit
+  bool ungrouped = false;  // boson probabilities: no multiplicity grouping
 };
 
 int fail(int code, const char* fmt, ...);
@@ -24,5 +28,14 @@ int gray_bits(int n, int algo);
 int min_chunk_log2(int nb);
 int pick_chunk_log2(int n, int algo, int requested);
 int perm_single(const double2* A, int n, int64_t lda, double2* out, const Opts& o, hipStream_t st, int cus);
+
+// Batched sweep over caller-built tables (plan.cpp).
+struct PlanImpl;
+double2* plan_table(PlanImpl* p, int64_t b);
+double2* plan_tables_base(PlanImpl* p);
+const std::vector<int64_t>& plan_table_offsets(PlanImpl* p);
+int plan_exec(PlanImpl* p, const double2* a, double2* out, hipStream_t st);
+int plan_ext_run(const int32_t* n_host, const int32_t* ncols_host, int64_t batch, const Opts& o, hipStream_t st,
+                 const std::function<int(PlanImpl*)>& fill, double2* out);
 
 }  // namespace ph

@@ -8,7 +8,8 @@ namespace ph {
 constexpr int NMAX = 52;       // largest n of the forward sweeps
 constexpr int NMAX_GRAD = 32;  // largest n of the backward sweep
 
-// Complex entries of the per-matrix table (n columns of n entries).
+// Complex entries of the per-matrix table (n columns of n entries; a table
+// with ncols < n columns uses the first ncols * n of them).
 inline size_t table_elems(int n) { return (size_t)n * n; }
 
 // Per-matrix descriptor used by the batched kernels (device memory).
@@ -16,8 +17,10 @@ struct MatDesc {
   int64_t a_off;       // offset of the input (row-major, contiguous) in the packed batch
   int64_t lda;         // row stride of the input (elements)
   double2* tab;        // table (table_elems(n) complex entries)
-  int32_t n;           // order
+  int32_t n;           // order (rows)
   int32_t c;           // log2 chunk length
+  int32_t ncols;       // columns the sweep walks (n, or fewer for a caller-built table)
+  int32_t reserved;
   int64_t part_begin;  // first partial slot of this matrix
   int64_t part_end;    // one past the last
   int64_t out_index;   // position of the result in the caller's output

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <sstream>
@@ -39,6 +40,9 @@ struct PlanImpl {
   std::vector<int32_t> n;
   std::vector<int64_t> off;   // element offsets of the matrices in A_packed
   std::vector<int32_t> c;     // chunk log2 per matrix (original order)
+  std::vector<int32_t> ncols; // columns walked per matrix (original order)
+  bool ext_tables = false;    // tables written by the caller: no prep kernel
+  std::vector<int64_t> tab_off;  // element offset of each table in d_tabs (original order)
   int64_t n_items = 0;
   char* dmem = nullptr;
   MatDesc* d_mats = nullptr;
@@ -153,8 +157,7 @@ static void save_cache_locked() {
 }
 
 int plan_build(const int32_t* n_host, const int64_t* off_host, int64_t batch, const Opts& o, const int32_t* c_force,
-               hipStream_t st, PlanImpl** out);
-int plan_exec(PlanImpl* p, const double2* a, double2* out, hipStream_t st);
+               hipStream_t st, PlanImpl** out, const int32_t* ncols_host = nullptr);
 
 // Time the batched sweep for each candidate chunk length on a synthetic batch
 // of order-n matrices (about 2^27 terms) and keep the fastest.
@@ -272,7 +275,7 @@ static hipError_t build_graph(PlanImpl* p, const Opts& o, const std::vector<std:
     k.params.sharedMemBytes = 0;
     if ((e = add(std::move(k))) != hipSuccess) return e;
   }
-  if (batch > 0) {
+  if (batch > 0 && !p->ext_tables) {
     KernelNode k;
     MatDesc* dm = p->d_mats;
     const double2* a = nullptr;
@@ -343,13 +346,18 @@ static hipError_t build_graph(PlanImpl* p, const Opts& o, const std::vector<std:
 }
 
 int plan_build(const int32_t* n_host, const int64_t* off_host, int64_t batch, const Opts& o, const int32_t* c_force,
-               hipStream_t st, PlanImpl** out) {
+               hipStream_t st, PlanImpl** out, const int32_t* ncols_host) {
   auto* p = new PlanImpl;
   hipGetDevice(&p->dev);
   p->algo = o.algo;
   p->plain = o.plain;
   p->batch = batch;
   p->n.assign(n_host, n_host + batch);
+  p->ext_tables = ncols_host != nullptr;
+  if (ncols_host)
+    p->ncols.assign(ncols_host, ncols_host + batch);
+  else
+    p->ncols = p->n;
   p->off.resize(batch);
   p->c.resize(batch);
   int64_t run = 0;
@@ -386,6 +394,11 @@ int plan_build(const int32_t* n_host, const int64_t* off_host, int64_t batch, co
       it = chosen.emplace(n, c).first;
     }
     p->c[b] = it->second;
+    if (p->ncols[b] != n) {
+      // fewer columns: keep at least 64 chunks (one per lane) where possible
+      const int nb = gray_bits(p->ncols[b], o.algo);
+      p->c[b] = std::max(min_chunk_log2(nb), std::min(p->c[b], std::max(min_chunk_log2(nb), nb - 6)));
+    }
   }
   // order: bucket (largest first), then n descending, then batch index
   std::vector<int64_t> order(batch);
@@ -403,14 +416,20 @@ int plan_build(const int32_t* n_host, const int64_t* off_host, int64_t batch, co
     m.a_off = p->off[b];
     m.lda = n;
     m.tab = reinterpret_cast<double2*>((uintptr_t)(tab_elems * sizeof(double2)));  // relocated below
+    if (p->ext_tables) {
+      if (p->tab_off.empty()) p->tab_off.assign(batch, 0);
+      p->tab_off[b] = (int64_t)tab_elems;
+    }
     m.n = n;
     m.c = p->c[b];
+    m.ncols = p->ncols[b];
+    m.reserved = 0;
     m.out_index = b;
     tab_elems += table_elems(n);
     const int64_t first = (int64_t)items.size();
     if (n > 0) {
       const int bk = bucket_of(n);
-      const int nb = gray_bits(n, o.algo);
+      const int nb = gray_bits(m.ncols, o.algo);
       const uint64_t nchunks = (uint64_t)1 << (nb - m.c);
       const int64_t nsuper = (int64_t)((nchunks + 63) / 64);
       for (int64_t s0 = 0; s0 < nsuper; s0 += 4) {
@@ -496,6 +515,12 @@ int plan_exec(PlanImpl* p, const double2* a, double2* out, hipStream_t st) {
   return PH_OK;
 }
 
+double2* plan_table(PlanImpl* p, int64_t b) { return p->d_tabs + p->tab_off[b]; }
+
+const std::vector<int64_t>& plan_table_offsets(PlanImpl* p) { return p->tab_off; }
+
+double2* plan_tables_base(PlanImpl* p) { return p->d_tabs; }
+
 static int check_batch_args(const int32_t* n_host, int64_t batch) {
   if (batch < 0) return fail(PH_EINVAL, "batch=%lld < 0", (long long)batch);
   if (batch > ((int64_t)1 << 30)) return fail(PH_EINVAL, "batch=%lld too large", (long long)batch);
@@ -557,9 +582,10 @@ struct CacheKey {
   int algo, plain, chunk, waves;
   std::vector<int32_t> n;
   std::vector<int64_t> off;
+  std::vector<int32_t> ncols;  // caller-built tables (empty for ordinary batches)
   bool operator==(const CacheKey& o) const {
     return dev == o.dev && st == o.st && algo == o.algo && plain == o.plain && chunk == o.chunk &&
-           waves == o.waves && n == o.n && off == o.off;
+           waves == o.waves && n == o.n && off == o.off && ncols == o.ncols;
   }
 };
 static std::mutex g_cache_mu;
@@ -607,3 +633,47 @@ extern "C" int ph_perm_batched(const ph_c128* A_packed, const int64_t* offsets_h
   }
   return ph_plan_execute(p, A_packed, out, stream);
 }
+
+namespace ph {
+
+// Batched sweep over caller-built tables (rows n[b], walked columns ncols[b]),
+// through the same plan cache: `fill` enqueues the writes of the tables
+// (plan_table / plan_tables_base) on `st`, then the plan runs and out[b]
+// receives 2^-(n[b]-1) (BB/FG) times the sweep's sum for table b.
+int plan_ext_run(const int32_t* n_host, const int32_t* ncols_host, int64_t batch, const Opts& o, hipStream_t st,
+                 const std::function<int(PlanImpl*)>& fill, double2* out) {
+  CacheKey key;
+  hipGetDevice(&key.dev);
+  key.st = st;
+  key.algo = o.algo;
+  key.plain = o.plain;
+  key.chunk = o.chunk_log2;
+  key.waves = o.waves;
+  key.n.assign(n_host, n_host + batch);
+  key.ncols.assign(ncols_host, ncols_host + batch);
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  PlanImpl* p = nullptr;
+  for (size_t i = 0; i < g_plans.size(); ++i) {
+    if (g_plans[i].first == key) {
+      auto hit = g_plans[i];
+      g_plans.erase(g_plans.begin() + i);
+      g_plans.push_back(hit);
+      p = hit.second;
+      break;
+    }
+  }
+  if (!p) {
+    int rc = plan_build(n_host, nullptr, batch, o, nullptr, st, &p, ncols_host);
+    if (rc) return rc;
+    if (g_plans.size() >= PLAN_CACHE) {
+      destroy_impl(g_plans.front().second);  // waits for its stream first
+      g_plans.erase(g_plans.begin());
+    }
+    g_plans.emplace_back(std::move(key), p);
+  }
+  int rc = fill(p);
+  if (rc) return rc;
+  return plan_exec(p, nullptr, out, st);
+}
+
+}  // namespace ph

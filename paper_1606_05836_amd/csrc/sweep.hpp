@@ -158,8 +158,9 @@ __device__ __forceinline__ void term(const double2 (&r)[N], double2& sb, bool ne
 // Row sums at the Gray word of index k0, from scratch, columns in order:
 //   BB/FG  r_i = a_i0 + sum_{j>=1} delta_j a_ij   (delta_j a_ij = (-delta_j/2) T[j]_i, exact)
 //   Ryser  r_i = sum_j [j in S] a_ij
+// over the table's ncols columns (N for a square matrix).
 template <int N, int ALGO>
-__device__ __forceinline__ void seed(double2 (&r)[N], uint64_t k0, const double2* T) {
+__device__ __forceinline__ void seed(double2 (&r)[N], uint64_t k0, const double2* T, int ncols) {
   const uint64_t g = k0 ^ (k0 >> 1);
   if constexpr (ALGO == ALGO_GLYNN) {
 #pragma unroll
@@ -169,7 +170,7 @@ __device__ __forceinline__ void seed(double2 (&r)[N], uint64_t k0, const double2
     for (int i = 0; i < N; ++i) r[i] = make_double2(0.0, 0.0);
   }
 #pragma unroll 1
-  for (int j = (ALGO == ALGO_GLYNN ? 1 : 0); j < N; ++j) {
+  for (int j = (ALGO == ALGO_GLYNN ? 1 : 0); j < ncols; ++j) {
     const int bit = ALGO == ALGO_GLYNN ? j - 1 : j;
     const bool set = (g >> bit) & 1;
     const double w = ALGO == ALGO_GLYNN ? (set ? 0.5 : -0.5) : (set ? 1.0 : 0.0);
@@ -214,15 +215,16 @@ struct Resident {
 };
 
 // One lane sweeps the chunk [k0, k0 + 2^c) and folds it into acc.
-// Requires LOGU <= c <= nb (c == 0 only when the formula has a single term).
+// Requires LOGU <= c <= nb (c == 0 only when the formula has a single term);
+// nb follows from the table's ncols columns (N for a square matrix).
 template <int N, int ALGO, int DR>
 __device__ __forceinline__ void sweep_chunk(uint64_t k0, int c, const Resident<N, ALGO, DR>& res, const double2* T,
-                                            dd2& acc, bool plain, bool active) {
+                                            dd2& acc, bool plain, bool active, int ncols = N) {
   using S = Shape<N, ALGO>;
   constexpr int LOGU = S::LOGU;
   constexpr int U = 1 << LOGU;
   double2 r[N];
-  seed<N, ALGO>(r, k0, T);
+  seed<N, ALGO>(r, k0, T, ncols);
   double2 sb = make_double2(0.0, 0.0);
   term<N>(r, sb, (k0 & 1) != 0);  // offset 0
   if constexpr (LOGU == 0) {

@@ -24,11 +24,12 @@ namespace ph {
 constexpr int BATCHED_DPP_NMAX = 40;
 
 template <int N, int ALGO>
-__device__ __forceinline__ void run_item(const double2* lds, int c, const WorkItem& w, int64_t slot,
+__device__ __forceinline__ void run_item(const double2* lds, int c, int ncols, const WorkItem& w, int64_t slot,
                                          double4* __restrict__ partials, int plain) {
   using S = Shape<N, ALGO>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint64_t nchunks = (uint64_t)1 << (S::NB - c);
+  const int nb = ALGO == ALGO_GLYNN ? ncols - 1 : ncols;
+  const uint64_t nchunks = (uint64_t)1 << (nb - c);
   // the item loop keeps extra state live: above n = BATCHED_DPP_NMAX every
   // column comes from LDS
   constexpr int DR = N > BATCHED_DPP_NMAX ? 0 : S::D;
@@ -37,16 +38,16 @@ __device__ __forceinline__ void run_item(const double2* lds, int c, const WorkIt
   dd2 acc = {0.0, 0.0, 0.0, 0.0};
   for (int r = wave; r < w.rounds; r += 4) {
     const uint64_t chunk = ((uint64_t)(w.super0 + r) << 6) + lane;
-    sweep_chunk<N, ALGO>(chunk << c, c, res, lds, acc, plain != 0, chunk < nchunks);
+    sweep_chunk<N, ALGO>(chunk << c, c, res, lds, acc, plain != 0, chunk < nchunks, ncols);
   }
   acc = wave_reduce(acc, plain != 0);
   if (lane == 0) partials[slot * 4 + wave] = make_double4(acc.hr, acc.lr, acc.hi, acc.li);
 }
 
 template <int NLO, int ALGO, int... Is>
-__device__ __forceinline__ void dispatch(int n, const double2* lds, int c, const WorkItem& w, int64_t slot,
+__device__ __forceinline__ void dispatch(int n, const double2* lds, int c, int ncols, const WorkItem& w, int64_t slot,
                                          double4* partials, int plain, std::integer_sequence<int, Is...>) {
-  ((n == NLO + Is ? (run_item<NLO + Is, ALGO>(lds, c, w, slot, partials, plain), 0) : 0), ...);
+  ((n == NLO + Is ? (run_item<NLO + Is, ALGO>(lds, c, ncols, w, slot, partials, plain), 0) : 0), ...);
 }
 
 // Templated on the bucket bounds so that each compilation defines distinct
@@ -65,9 +66,9 @@ __global__ __launch_bounds__(256) void k_sweep_batched(const MatDesc* __restrict
     if (it >= item_end) break;
     const WorkItem w = items[it];
     const MatDesc m = mats[w.mat];
-    for (int e = threadIdx.x; e < m.n * m.n; e += blockDim.x) lds_tab[e] = m.tab[e];
+    for (int e = threadIdx.x; e < m.n * m.ncols; e += blockDim.x) lds_tab[e] = m.tab[e];
     __syncthreads();
-    dispatch<NLO, ALGO>(m.n, lds_tab, m.c, w, it, partials, plain,
+    dispatch<NLO, ALGO>(m.n, lds_tab, m.c, m.ncols, w, it, partials, plain,
                         std::make_integer_sequence<int, NHI - NLO + 1>{});
     __syncthreads();  // LDS and s_item are reused by the next item
   }

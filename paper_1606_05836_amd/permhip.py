@@ -21,6 +21,7 @@ PH_GLYNN, PH_RYSER = 0, 1
 PH_ACC_DD, PH_ACC_PLAIN = 0, 1
 PH_OK, PH_EINVAL, PH_ERANGE, PH_ENOMEM, PH_EHIP, PH_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PH_NMAX, PH_NMAX_GRAD = 52, 32
+PH_FLAG_UNGROUPED = 1
 
 EXPORTS = ("ph_perm", "ph_perm_batched", "ph_plan_create", "ph_plan_execute", "ph_plan_destroy",
            "ph_perm_grad", "ph_boson_probs", "ph_boson_probs_grad", "ph_fp64_peak", "ph_last_error",
@@ -78,10 +79,11 @@ def check(rc: int) -> None:
         raise PermhipError(rc, lib().ph_last_error().decode())
 
 
-def opts(algo: str | int = "glynn", accum: str | int = "dd", chunk_log2: int = 0, waves: int = 0) -> PhOpts:
+def opts(algo: str | int = "glynn", accum: str | int = "dd", chunk_log2: int = 0, waves: int = 0,
+         flags: int = 0) -> PhOpts:
     a = {"glynn": PH_GLYNN, "ryser": PH_RYSER}.get(algo, algo)
     c = {"dd": PH_ACC_DD, "plain": PH_ACC_PLAIN}.get(accum, accum)
-    return PhOpts(int(a), int(c), int(chunk_log2), int(waves), 0)
+    return PhOpts(int(a), int(c), int(chunk_log2), int(waves), int(flags))
 
 
 def _stream(t: torch.Tensor):
@@ -244,18 +246,20 @@ def _need_square_u(u: torch.Tensor):
     return u if u.stride(1) == 1 else u.contiguous()
 
 
-def boson_probs(u: torch.Tensor, in_modes, patterns, algo="glynn", accum="dd") -> torch.Tensor:
+def boson_probs(u: torch.Tensor, in_modes, patterns, algo="glynn", accum="dd", ungrouped: bool = False) -> torch.Tensor:
     """Eq. (1) probabilities Pr[S -> T_p] for each row T_p of `patterns`.
 
     u: m x m complex128 CUDA tensor indexed [output mode, input mode];
     in_modes: the n input modes (repeats for multi-photon inputs);
-    patterns: (n_patterns, n) output modes (repeats for collisions)."""
+    patterns: (n_patterns, n) output modes (repeats for collisions);
+    ungrouped: one full sweep per pattern instead of the multiplicity-grouped
+    sweeps (PH_FLAG_UNGROUPED)."""
     u = _need_square_u(u)
     m = u.shape[0]
     ins, pats = _modes(in_modes, patterns, m)
     n, npat = ins.shape[0], pats.shape[0]
     probs = torch.empty(npat, dtype=torch.float64, device=u.device)
-    o = opts(algo, accum)
+    o = opts(algo, accum, flags=PH_FLAG_UNGROUPED if ungrouped else 0)
     check(lib().ph_boson_probs(_ptr(u), m, u.stride(0), _i32p(ins), n, _i32p(pats), npat, _ptr(probs),
                                ctypes.byref(o), _stream(u)))
     return probs

@@ -70,6 +70,27 @@ def test_collisions_against_multiplicity_route(ph):
         assert rel(pr[k], e) <= 1e-11, (list(p), pr[k], e)
 
 
+def test_grouped_sweeps_against_multiplicity_route(ph):
+    # patterns with 5+ single-photon modes and doubly / triply occupied modes
+    # take the multiplicity-grouped sweeps; the oracle's grouped Ryser route
+    # is independent of them
+    m, n = 40, 12
+    u = I.haar(m, 18)
+    rng = np.random.default_rng(19)
+    pats = []
+    for c2, c3 in [(1, 0), (2, 1), (0, 1), (3, 0), (1, 1), (2, 0)]:
+        modes = rng.choice(m, n - c2 - 2 * c3, replace=False)
+        pats.append(np.sort(np.concatenate([modes, modes[:c2], np.repeat(modes[c2:c2 + c3], 2)])))
+    pats = np.stack(pats)
+    ins = list(range(n))
+    pr = ph.boson_probs(cuda(u), ins, pats).cpu().numpy()
+    pu = ph.boson_probs(cuda(u), ins, pats, ungrouped=True).cpu().numpy()
+    for k, p in enumerate(pats):
+        e = float(O.prob_multiplicity(u, ins, p))
+        assert rel(pr[k], e) <= 1e-11, (list(p), pr[k], e)
+        assert rel(pu[k], e) <= 1e-11, (list(p), pu[k], e)
+
+
 def test_reduced_workload_against_oracle(ph):
     # the full workload's recipe (Haar(900), collision patterns) at 16 photons
     u, ins, pats = I.config5_workload(n=16, patterns=8)
@@ -181,11 +202,12 @@ def test_full_workload_forward_paths_agree(ph, full_workload):
     # batched forward sweep vs the gradient sweep's permanents: two kernels
     # with different chunkings, each within PROB_TOL of the exact value
     assert np.max(np.abs(pf - pg) / pf) <= 2 * PROB_TOL
-    # the permanents of the gathered matrices through the plain batched entry point
+    # the permanents of the gathered matrices through the plain batched entry
+    # point (full sweeps) against the multiplicity-grouped sweeps
     a = np.stack([O.gather_u_st(u, ins, p) for p in pats])
     per = ph.perm_batched(cuda(a)).cpu().numpy()
     d = np.array([O.occupation_factorials(ins) * O.occupation_factorials(p) for p in pats], dtype=np.float64)
-    assert np.max(np.abs(np.abs(per) ** 2 / d - pf) / pf) <= 1e-13
+    assert np.max(np.abs(np.abs(per) ** 2 / d - pf) / pf) <= 2 * PROB_TOL
 
 
 def test_full_workload_row_and_column_laplace(ph, full_workload):
@@ -213,6 +235,14 @@ def test_full_workload_row_and_column_laplace(ph, full_workload):
     tol_k = PERM_TOL * mag.sum(axis=0) + PROB_TOL * total
     assert np.all(np.abs(col - total) <= tol_k)
     assert n == du.shape[1]
+
+
+def test_full_workload_grouped_against_ungrouped(ph, full_workload):
+    # multiplicity-grouped sweeps (fewer terms) against one full sweep per
+    # pattern: two different sums of the same permanents
+    u, ins, pats, w, pf, pg, du = full_workload
+    pu = ph.boson_probs(cuda(u), ins, pats, ungrouped=True).cpu().numpy()
+    assert np.max(np.abs(pu - pf) / pf) <= 2 * PROB_TOL
 
 
 def test_full_workload_phase_invariance(ph, full_workload):
