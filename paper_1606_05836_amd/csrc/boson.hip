@@ -16,6 +16,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -28,6 +29,9 @@ namespace ph {
 
 int perm_grad_launch(const double2* A, int n, int64_t batch, const double2* gout, double2* pout, double2* grad,
                      const Opts& o, hipStream_t st, int cus);
+int grad_rows(int n);
+int grad_sweep(const double2* tabs, int n, int ncols, int64_t batch, const double2* gout, double2* pout,
+               double2* grad, const Opts& o, hipStream_t st, int cus);
 
 // a[p][i][k] = U[T_p[i], S[k]]
 __global__ void k_boson_gather(const double2* __restrict__ u, int64_t ldu, const int32_t* __restrict__ in_modes,
@@ -277,14 +281,16 @@ __global__ void k_boson_vtab(const double2* __restrict__ u, int64_t ldu, const i
   }
 }
 
-// perms[p] = sum over the pattern's sweeps, in order, of w_v * vout[v]
-__global__ void k_boson_combine(const double2* __restrict__ vout, const double* __restrict__ w,
-                                const int32_t* __restrict__ pv, int64_t npat, int plain, double2* __restrict__ perms) {
+// perms[p] = sum over the pattern's sweeps, in order, of w_v * vout[vpos[v]]
+// (vpos NULL: vout in sweep order)
+__global__ void k_boson_combine(const double2* __restrict__ vout, const int32_t* __restrict__ vpos,
+                                const double* __restrict__ w, const int32_t* __restrict__ pv, int64_t npat, int plain,
+                                double2* __restrict__ perms) {
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= npat) return;
   dd2 s = {0.0, 0.0, 0.0, 0.0};
   for (int32_t v = pv[p]; v < pv[p + 1]; ++v) {
-    const double2 x = vout[v];
+    const double2 x = vout[vpos ? vpos[v] : v];
     if (plain) {
       s.hr = fma(w[v], x.x, s.hr);
       s.hi = fma(w[v], x.y, s.hi);
@@ -432,10 +438,245 @@ static int boson_perms_grouped(hipStream_t st, const ph_c128* U, int64_t ldu, co
   og.algo = PH_GLYNN;
   rc = plan_ext_run(ns.data(), sw.vncols.data(), V, og, st, fill, vout);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_boson_combine, dim3((unsigned)((npat + 255) / 256)), dim3(256), 0, st, vout, d_w, I32(7),
-                     npat, o.plain ? 1 : 0, perms);
+  hipLaunchKernelGGL(k_boson_combine, dim3((unsigned)((npat + 255) / 256)), dim3(256), 0, st, vout,
+                     (const int32_t*)nullptr, d_w, I32(7), npat, o.plain ? 1 : 0, perms);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? PH_OK : hip_fail(e, "boson combine launch");
+}
+
+// ------------------------------------------- gradient of the grouped sweeps
+//
+// The gradient sweep over sweep v's n x n1 table gives conj(dF_v / dC_v) with
+// F_v = 2^-(n-1) G_v and C_v its columns.  Column 0 is b_l0 + sum_c coef_c b_c
+// and column j >= 1 is b_(mode j), so for output mode x of pattern p
+//   conj(dPer_p / db_x) = sum_v w_v [ sum_{j: mode j = x} conj(dF_v/dC_v[:, j])
+//                                     + sum_{c: coll c = x} coef_c conj(dF_v/dC_v[:, 0]) ],
+// a list of (entry of conj(dF), coefficient) per (pattern, mode) summed in a
+// fixed order; dU[x][k] = sum over patterns holding x of g_p conj(dPer_p/db_x[k]).
+
+// Gradient tables of one group of sweeps with equal column counts: like
+// k_boson_vtab, rows padded to `rows` with zeros, T[j * rows + i].
+__global__ void k_boson_gtab(const double2* __restrict__ u, int64_t ldu, const int32_t* __restrict__ in_modes, int n,
+                             int rows, const int32_t* __restrict__ vlist, const int32_t* __restrict__ vcol, int ncols,
+                             const int32_t* __restrict__ vcoef, const int32_t* __restrict__ vncoef,
+                             const int32_t* __restrict__ colmodes, const int32_t* __restrict__ collmodes,
+                             const double* __restrict__ coefs, double2* __restrict__ tabs) {
+  const int64_t b = blockIdx.x;
+  const int32_t v = vlist[b];
+  const int32_t* cm = colmodes + vcol[v];
+  const int c0 = vcoef[v], nc = vncoef[v];
+  double2* t = tabs + b * ncols * rows;
+  for (int e = threadIdx.x; e < ncols * rows; e += blockDim.x) {
+    const int j = e / rows, i = e % rows;
+    double2 val = make_double2(0.0, 0.0);
+    if (i < n) {
+      const int64_t s = in_modes[i];
+      val = u[(int64_t)cm[j] * ldu + s];
+      if (j == 0) {
+        for (int q = 0; q < nc; ++q) {
+          const double w = coefs[c0 + q];
+          const double2 bq = u[(int64_t)collmodes[c0 + q] * ldu + s];
+          val.x = fma(w, bq.x, val.x);
+          val.y = fma(w, bq.y, val.y);
+        }
+      } else {
+        val = make_double2(-2.0 * val.x, -2.0 * val.y);
+      }
+    }
+    t[e] = val;
+  }
+}
+
+// D[e][k] = sum over entry e's contributions, in order, of coef * cm[pos + k * stride]
+__global__ void k_boson_class_grad(const double2* __restrict__ cm, const int32_t* __restrict__ cstart,
+                                   const int64_t* __restrict__ cpos, const int32_t* __restrict__ cstride,
+                                   const double* __restrict__ ccoef, int64_t nent, int n, double2* __restrict__ D) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nent * n) return;
+  const int64_t e = t / n;
+  const int k = (int)(t % n);
+  double sr = 0.0, si = 0.0;
+  for (int32_t q = cstart[e]; q < cstart[e + 1]; ++q) {
+    const double2 x = cm[cpos[q] + (int64_t)k * cstride[q]];
+    sr = fma(ccoef[q], x.x, sr);
+    si = fma(ccoef[q], x.y, si);
+  }
+  D[t] = make_double2(sr, si);
+}
+
+// dU[r][k] = sum over the entries of output mode r, in order, of g_p D[e][k]
+__global__ void k_boson_scatter_entries(const double2* __restrict__ D, const double2* __restrict__ gperm,
+                                        const int32_t* __restrict__ ent_pat, const int32_t* __restrict__ mstart,
+                                        const int32_t* __restrict__ mlist, int m, int n, double2* __restrict__ du,
+                                        int64_t lddu) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)m * n) return;
+  const int r = (int)(t / n), k = (int)(t % n);
+  double sr = 0.0, si = 0.0;
+  for (int32_t q = mstart[r]; q < mstart[r + 1]; ++q) {
+    const int32_t e = mlist[q];
+    const double2 g = gperm[ent_pat[e]];
+    const double2 d = D[(int64_t)e * n + k];
+    sr += g.x * d.x - g.y * d.y;
+    si += g.x * d.y + g.y * d.x;
+  }
+  du[(int64_t)r * lddu + k] = make_double2(sr, si);
+}
+
+static int boson_grad_grouped(hipStream_t st, const ph_c128* U, int32_t m, int64_t ldu, const int32_t* in_modes,
+                              int n, const int32_t* patterns, int64_t npat, const double* weights, double* probs,
+                              ph_c128* dU, int64_t lddu, const Opts& o, int cus) {
+  if ((int64_t)npat * n >= ((int64_t)1 << 31) - 1) return fail(PH_ERANGE, "n_patterns * n too large");
+  Sweeps sw;
+  plan_sweeps(patterns, n, npat, o.ungrouped, &sw);
+  const int64_t V = (int64_t)sw.w.size();
+  const int rows = grad_rows(n);
+  // groups of sweeps by column count; position of each sweep's results
+  std::map<int, std::vector<int32_t>> groups;
+  for (int64_t v = 0; v < V; ++v) groups[sw.vncols[v]].push_back((int32_t)v);
+  std::vector<int32_t> vlist, vpos(V);
+  std::vector<int64_t> moff(V);
+  int64_t mtot = 0, max_tab = 0;
+  for (auto& g : groups) {
+    max_tab = std::max<int64_t>(max_tab, (int64_t)g.second.size() * g.first * rows);
+    for (int32_t v : g.second) {
+      vpos[v] = (int32_t)vlist.size();
+      vlist.push_back(v);
+      moff[v] = mtot;
+      mtot += (int64_t)n * g.first;
+    }
+  }
+  // (pattern, output mode) entries and their contributions
+  std::vector<int32_t> ent_pat, ent_mode;
+  std::vector<std::vector<std::tuple<int64_t, int32_t, double>>> contrib;
+  for (int64_t p = 0; p < npat; ++p) {
+    const int32_t* t = patterns + p * n;
+    const int32_t e0 = (int32_t)ent_pat.size();
+    auto entry = [&](int32_t mode) -> int32_t {
+      for (int32_t e = e0; e < (int32_t)ent_pat.size(); ++e)
+        if (ent_mode[e] == mode) return e;
+      ent_pat.push_back((int32_t)p);
+      ent_mode.push_back(mode);
+      contrib.emplace_back();
+      return (int32_t)ent_pat.size() - 1;
+    };
+    for (int i = 0; i < n; ++i) entry(t[i]);
+    for (int32_t v = sw.pv[p]; v < sw.pv[p + 1]; ++v) {
+      const int nc = sw.vncols[v];
+      const int32_t* cmodes = sw.colmodes.data() + sw.vcol[v];
+      for (int j = 0; j < nc; ++j) contrib[entry(cmodes[j])].emplace_back(moff[v] + j, nc, sw.w[v]);
+      for (int q = 0; q < sw.vncoef[v]; ++q) {
+        const int32_t cidx = sw.vcoef[v] + q;
+        contrib[entry(sw.collmodes[cidx])].emplace_back(moff[v], nc, sw.w[v] * sw.coefs[cidx]);
+      }
+    }
+  }
+  const int64_t E = (int64_t)ent_pat.size();
+  std::vector<int32_t> cstart(E + 1, 0), cstride;
+  std::vector<int64_t> cpos;
+  std::vector<double> ccoef;
+  for (int64_t e = 0; e < E; ++e) {
+    cstart[e] = (int32_t)cpos.size();
+    for (auto& c : contrib[e]) {
+      cpos.push_back(std::get<0>(c));
+      cstride.push_back(std::get<1>(c));
+      ccoef.push_back(std::get<2>(c));
+    }
+  }
+  cstart[E] = (int32_t)cpos.size();
+  const int64_t C = (int64_t)cpos.size();
+  std::vector<int32_t> mstart(m + 1, 0), mlist(E);
+  for (int64_t e = 0; e < E; ++e) mstart[ent_mode[e] + 1]++;
+  for (int r = 0; r < m; ++r) mstart[r + 1] += mstart[r];
+  {
+    std::vector<int32_t> fill(mstart.begin(), mstart.end() - 1);
+    for (int64_t e = 0; e < E; ++e) mlist[fill[ent_mode[e]]++] = (int32_t)e;
+  }
+  // device layout (workspace slot 2)
+  auto one = [](size_t x) { return std::max<size_t>(x, 1); };
+  enum { P_IN, P_PAT, P_VCOL, P_VCOEF, P_VNCOEF, P_COLM, P_COLLM, P_PV, P_VLIST, P_VPOS, P_CSTART, P_CSTRIDE,
+         P_ENTPAT, P_MSTART, P_MLIST, P_COEFS, P_W, P_CCOEF, P_CPOS, NP_UP,
+         B_TAB = NP_UP, B_CM, B_POUT, B_PERMS, B_GPERM, B_D, NB_ALL };
+  size_t sz[NB_ALL] = {};
+  sz[P_IN] = one(n) * 4;
+  sz[P_PAT] = one(npat * n) * 4;
+  sz[P_VCOL] = sz[P_VCOEF] = sz[P_VNCOEF] = one(V) * 4;
+  sz[P_COLM] = one(sw.colmodes.size()) * 4;
+  sz[P_COLLM] = one(sw.collmodes.size()) * 4;
+  sz[P_PV] = one(npat + 1) * 4;
+  sz[P_VLIST] = sz[P_VPOS] = one(V) * 4;
+  sz[P_CSTART] = one(E + 1) * 4;
+  sz[P_CSTRIDE] = one(C) * 4;
+  sz[P_ENTPAT] = one(E) * 4;
+  sz[P_MSTART] = one(m + 1) * 4;
+  sz[P_MLIST] = one(E) * 4;
+  sz[P_COEFS] = one(sw.coefs.size()) * 8;
+  sz[P_W] = one(V) * 8;
+  sz[P_CCOEF] = one(C) * 8;
+  sz[P_CPOS] = one(C) * 8;
+  sz[B_TAB] = one(max_tab) * 16;
+  sz[B_CM] = one(mtot) * 16;
+  sz[B_POUT] = one(V) * 16;
+  sz[B_PERMS] = sz[B_GPERM] = one(npat) * 16;
+  sz[B_D] = one(E * n) * 16;
+  size_t off[NB_ALL + 1];
+  off[0] = 0;
+  for (int q = 0; q < NB_ALL; ++q) off[q + 1] = off[q] + up256(sz[q]);
+  void* ws = nullptr;
+  int rc = workspace_slot(st, off[NB_ALL], 2, &ws);
+  if (rc) return rc;
+  char* d = static_cast<char*>(ws);
+  auto I32 = [&](int q) { return reinterpret_cast<int32_t*>(d + off[q]); };
+  auto F64 = [&](int q) { return reinterpret_cast<double*>(d + off[q]); };
+  auto C128 = [&](int q) { return reinterpret_cast<double2*>(d + off[q]); };
+  const Piece pc[NP_UP] = {{in_modes, (size_t)n * 4},
+                           {patterns, (size_t)(npat * n) * 4},
+                           {sw.vcol.data(), (size_t)V * 4},
+                           {sw.vcoef.data(), (size_t)V * 4},
+                           {sw.vncoef.data(), (size_t)V * 4},
+                           {sw.colmodes.data(), sw.colmodes.size() * 4},
+                           {sw.collmodes.data(), sw.collmodes.size() * 4},
+                           {sw.pv.data(), (size_t)(npat + 1) * 4},
+                           {vlist.data(), (size_t)V * 4},
+                           {vpos.data(), (size_t)V * 4},
+                           {cstart.data(), (size_t)(E + 1) * 4},
+                           {cstride.data(), (size_t)C * 4},
+                           {ent_pat.data(), (size_t)E * 4},
+                           {mstart.data(), (size_t)(m + 1) * 4},
+                           {mlist.data(), (size_t)E * 4},
+                           {sw.coefs.data(), sw.coefs.size() * 8},
+                           {sw.w.data(), (size_t)V * 8},
+                           {ccoef.data(), (size_t)C * 8},
+                           {cpos.data(), (size_t)C * 8}};
+  if ((rc = upload_at(st, d, off, pc, NP_UP))) return rc;
+  // one gradient sweep launch per column count
+  int64_t first = 0;
+  for (auto& g : groups) {
+    const int ncols = g.first;
+    const int64_t cnt = (int64_t)g.second.size();
+    hipLaunchKernelGGL(k_boson_gtab, dim3((unsigned)cnt), dim3(256), 0, st, reinterpret_cast<const double2*>(U), ldu,
+                       I32(P_IN), n, rows, I32(P_VLIST) + first, I32(P_VCOL), ncols, I32(P_VCOEF), I32(P_VNCOEF),
+                       I32(P_COLM), I32(P_COLLM), F64(P_COEFS), C128(B_TAB));
+    rc = grad_sweep(C128(B_TAB), n, ncols, cnt, nullptr, C128(B_POUT) + first, C128(B_CM) + moff[g.second[0]], o,
+                    st, cus);
+    if (rc) return rc;
+    first += cnt;
+  }
+  const unsigned pb = (unsigned)((npat + 255) / 256);
+  hipLaunchKernelGGL(k_boson_combine, dim3(pb), dim3(256), 0, st, C128(B_POUT), I32(P_VPOS), F64(P_W), I32(P_PV),
+                     npat, o.plain ? 1 : 0, C128(B_PERMS));
+  hipLaunchKernelGGL(k_boson_normalize, dim3(pb), dim3(256), 0, st, C128(B_PERMS), I32(P_IN), I32(P_PAT), n, npat,
+                     weights, probs, C128(B_GPERM));
+  if (E > 0)
+    hipLaunchKernelGGL(k_boson_class_grad, dim3((unsigned)((E * n + 255) / 256)), dim3(256), 0, st, C128(B_CM),
+                       I32(P_CSTART), reinterpret_cast<int64_t*>(d + off[P_CPOS]), I32(P_CSTRIDE), F64(P_CCOEF), E, n,
+                       C128(B_D));
+  const int64_t tot = (int64_t)m * n;
+  hipLaunchKernelGGL(k_boson_scatter_entries, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, C128(B_D),
+                     C128(B_GPERM), I32(P_ENTPAT), I32(P_MSTART), I32(P_MLIST), m, n, reinterpret_cast<double2*>(dU),
+                     lddu);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? PH_OK : hip_fail(e, "boson grad launch");
 }
 
 }  // namespace ph
@@ -483,6 +724,8 @@ extern "C" int ph_boson_probs_grad(const ph_c128* U, int32_t m, int64_t ldu, con
   const int cus = num_cus();
   if (cus <= 0) return PH_EUNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
+  if (n >= GROUP_MIN_SINGLES + 1 && n_patterns > 0)
+    return boson_grad_grouped(st, U, m, ldu, in_modes, n, patterns, n_patterns, weights, probs, dU, lddu, o, cus);
   BosonBufs b;
   if ((rc = boson_setup(st, U, m, ldu, in_modes, n, patterns, n_patterns, true, &b))) return rc;
   if (n_patterns > 0) {

@@ -103,8 +103,9 @@ struct GradShape {
 };
 
 struct GradArgs {
-  const double2* tabs;  // per matrix: n columns x ROWS rows (zero padded)
+  const double2* tabs;  // per matrix: ncols columns x ROWS rows (zero padded)
   int n, c;
+  int ncols;            // columns the sweep walks (n for a square matrix)
   int64_t nsuper;       // super-chunks per matrix (64/H chunks each)
   int s_per;            // units (slices) per matrix
   int64_t units;        // batch * s_per
@@ -234,13 +235,13 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
   using GS = GradShape<M, H>;
   constexpr int K = GS::K, ROWS = GS::ROWS, NG = GS::NG;
   extern __shared__ double lds[];
-  double2* tab = reinterpret_cast<double2*>(lds);  // n * ROWS complex
-  double* stage_all = lds + 2 * (size_t)a.n * ROWS;  // 4 waves * 64 * SS complex
+  double2* tab = reinterpret_cast<double2*>(lds);  // ncols * ROWS complex
+  double* stage_all = lds + 2 * (size_t)a.ncols * ROWS;  // 4 waves * 64 * SS complex
   __shared__ int64_t s_unit;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sig = lane % H, grp = lane / H;
   double* stage = stage_all + wave * 2 * 64 * GS::SS;
-  const int n = a.n, c = a.c, nb = n - 1;
+  const int n = a.n, nc = a.ncols, c = a.c, nb = nc - 1;
   const int row0 = sig * M;
   const bool out_lane = lane < 2 * ROWS;
   for (;;) {
@@ -249,14 +250,14 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
     const int64_t u = s_unit;
     if (u >= a.units) break;
     const int64_t mat = u / a.s_per, sl = u % a.s_per;
-    const double2* gtab = a.tabs + (size_t)mat * n * ROWS;
-    for (int e = threadIdx.x; e < n * ROWS; e += blockDim.x) tab[e] = gtab[e];
+    const double2* gtab = a.tabs + (size_t)mat * nc * ROWS;
+    for (int e = threadIdx.x; e < nc * ROWS; e += blockDim.x) tab[e] = gtab[e];
     __syncthreads();
     const int64_t slot = u * 4 + wave;
-    double* ghat = reinterpret_cast<double*>(a.ghat + (size_t)slot * n * ROWS);
+    double* ghat = reinterpret_cast<double*>(a.ghat + (size_t)slot * nc * ROWS);
     // each lane zeroes the accumulator entries it will own
     if (out_lane)
-      for (int j = 0; j < n; ++j) ghat[j * 2 * ROWS + lane] = 0.0;
+      for (int j = 0; j < nc; ++j) ghat[j * 2 * ROWS + lane] = 0.0;
     GradLane<M, H> L;
 #pragma unroll
     for (int b = 0; b < K; ++b)
@@ -281,7 +282,7 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
 #pragma unroll
       for (int ii = 0; ii < M; ++ii) L.r[ii] = tab[row0 + ii];
 #pragma unroll 1
-      for (int j = 1; j < n; ++j) grad_update<M, H>(L, ((g0 >> (j - 1)) & 1) ? 0.5 : -0.5, tab + j * ROWS + row0);
+      for (int j = 1; j < nc; ++j) grad_update<M, H>(L, ((g0 >> (j - 1)) & 1) ? 0.5 : -0.5, tab + j * ROWS + row0);
 #pragma unroll
       for (int ii = 0; ii < M; ++ii) {
         if (row0 + ii >= n) L.r[ii] = make_double2(1.0, 0.0);  // padding rows
@@ -354,7 +355,7 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
       const uint64_t gl = kl ^ (kl >> 1);
       group_sum_add<M, H>(L.W, 1.0, stage, ghat);  // column 0: delta_0 = +1
 #pragma unroll 1
-      for (int j = K + 1; j < n; ++j)
+      for (int j = K + 1; j < nc; ++j)
         group_sum_add<M, H>(L.W, ((gl >> (j - 1)) & 1) ? -1.0 : 1.0, stage, ghat + (size_t)j * 2 * ROWS);
 #pragma unroll
       for (int b = 0; b < K; ++b) {
@@ -370,11 +371,11 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
     if (out_lane) {
 #pragma unroll
       for (int q = 0; q < GS::R; ++q)
-        if (K + q + 1 < n) ghat[(size_t)(K + q + 1) * 2 * ROWS + lane] += bacc[q];
+        if (K + q + 1 < nc) ghat[(size_t)(K + q + 1) * 2 * ROWS + lane] += bacc[q];
     }
 #pragma unroll
     for (int b = 0; b < K; ++b)
-      if (b + 1 < n) group_sum_add<M, H>(L.G[b], 1.0, stage, ghat + (size_t)(b + 1) * 2 * ROWS);
+      if (b + 1 < nc) group_sum_add<M, H>(L.G[b], 1.0, stage, ghat + (size_t)(b + 1) * 2 * ROWS);
     if (sig != 0) acc = dd2{0.0, 0.0, 0.0, 0.0};
     acc = wave_reduce(acc, a.plain != 0);
     if (lane == 0) a.fparts[slot] = make_double4(acc.hr, acc.lr, acc.hi, acc.li);
@@ -399,19 +400,20 @@ __global__ void k_grad_prep(const double2* __restrict__ a, int n, int rows, doub
   }
 }
 
-// Per matrix: M = 2^-(n-1) sum over the (unit, wave) accumulators in order,
-// grad = g * conj(M), perm = 2^-(n-1) sum of forward partials.
-__global__ void k_grad_finalize(const double2* __restrict__ ghat, const double4* __restrict__ fparts, int n, int rows,
-                                int s_per, int plain, const double2* __restrict__ gout, double2* __restrict__ pout,
-                                double2* __restrict__ grad) {
+// Per matrix: M = 2^-(n-1) sum over the (unit, wave) accumulators in order
+// (n x ncols, row-major), grad = g * conj(M), perm = 2^-(n-1) sum of forward
+// partials.
+__global__ void k_grad_finalize(const double2* __restrict__ ghat, const double4* __restrict__ fparts, int n,
+                                int ncols, int rows, int s_per, int plain, const double2* __restrict__ gout,
+                                double2* __restrict__ pout, double2* __restrict__ grad) {
   const int64_t mat = blockIdx.x;
   const int64_t slots = (int64_t)s_per * 4, first = mat * slots;
   const double2 g = gout ? gout[mat] : make_double2(1.0, 0.0);
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int i = e / n, j = e % n;
+  for (int e = threadIdx.x; e < n * ncols; e += blockDim.x) {
+    const int i = e / ncols, j = e % ncols;
     dd2 s = {0.0, 0.0, 0.0, 0.0};
     for (int64_t q = 0; q < slots; ++q) {
-      const double2 v = ghat[(first + q) * n * rows + (size_t)j * rows + i];
+      const double2 v = ghat[(first + q) * ncols * rows + (size_t)j * rows + i];
       if (plain) {
         s.hr += v.x;
         s.hi += v.y;
@@ -422,7 +424,7 @@ __global__ void k_grad_finalize(const double2* __restrict__ ghat, const double4*
     const double mr = ldexp(s.hr, -(n - 1)) + ldexp(s.lr, -(n - 1));
     const double mi = ldexp(s.hi, -(n - 1)) + ldexp(s.li, -(n - 1));
     // g * conj(M)
-    grad[mat * n * n + e] = make_double2(g.x * mr + g.y * mi, g.y * mr - g.x * mi);
+    grad[mat * n * ncols + e] = make_double2(g.x * mr + g.y * mi, g.y * mr - g.x * mi);
   }
   if (pout && threadIdx.x == 0) {
     dd2 s = {0.0, 0.0, 0.0, 0.0};
@@ -497,26 +499,28 @@ static GradLayout grad_layout(int n) {
   return GradLayout{0, 0, 0, nullptr};
 }
 
-// Enqueue the gradient of `batch` n x n matrices (device pointers).
-int perm_grad_launch(const double2* A, int n, int64_t batch, const double2* gout, double2* pout, double2* grad,
-                     const Opts& o, hipStream_t st, int cus) {
+int grad_rows(int n) {
+  const GradLayout lay = grad_layout(n);
+  return lay.H * lay.M;
+}
+
+// Gradient sweeps over prebuilt tables: `batch` tables of ncols columns x
+// grad_rows(n) rows (T[0] = column 0, T[j] = -2 column j, rows >= n zero),
+// packed back to back.  grad (n x ncols per matrix) = g * conj(M), pout the
+// 2^-(n-1)-scaled sums.  5 <= ncols <= n unless ncols == n.
+int grad_sweep(const double2* tabs, int n, int ncols, int64_t batch, const double2* gout, double2* pout,
+               double2* grad, const Opts& o, hipStream_t st, int cus) {
   if (batch == 0) return PH_OK;
-  hipError_t e;
-  if (n == 1) {
-    hipLaunchKernelGGL(k_grad_n1, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, st, A, batch, gout, pout,
-                       grad);
-    e = hipGetLastError();
-    return e == hipSuccess ? PH_OK : hip_fail(e, "grad launch");
-  }
   const GradLayout lay = grad_layout(n);
   if (!lay.kern) return fail(PH_ERANGE, "no gradient kernel for n=%d", n);
-  const int K = lay.K, rows = lay.H * lay.M, ng = 64 / lay.H, nb = n - 1;
+  const int K = lay.K, rows = lay.H * lay.M, ng = 64 / lay.H, nb = ncols - 1;
+  if (nb < K) return fail(PH_EINVAL, "gradient sweep over %d columns of %d rows", ncols, n);
   int c = o.chunk_log2 > 0 ? o.chunk_log2 : std::min(10, nb - 4);
   c = std::max(K, std::min(c, nb));  // K >= LOGP, so a chunk holds whole runs
   const int64_t nsuper = (int64_t)((((uint64_t)1 << (nb - c)) + ng - 1) / ng);
-  const size_t lds = (size_t)n * rows * sizeof(double2) + 4 * 64 * (size_t)(lay.M | 1) * sizeof(double2);
+  const size_t lds = (size_t)ncols * rows * sizeof(double2) + 4 * 64 * (size_t)(lay.M | 1) * sizeof(double2);
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lay.kern, 256, lds);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lay.kern, 256, lds);
   if (e != hipSuccess) return hip_fail(e, "occupancy");
   per_cu = std::max(1, per_cu);
   if (o.waves > 0) per_cu = std::min(per_cu, o.waves);
@@ -526,37 +530,55 @@ int perm_grad_launch(const double2* A, int n, int64_t batch, const double2* gout
   int64_t s_per = std::max<int64_t>(1, (4 * blocks_full + batch - 1) / batch);
   s_per = std::min<int64_t>(s_per, std::max<int64_t>(1, nsuper / 4));
   const int64_t units = batch * s_per;
-  const size_t tab_elems = (size_t)batch * n * rows;
-  const size_t ghat_elems = (size_t)units * 4 * n * rows;
-  const size_t off_g = ((tab_elems * sizeof(double2)) + 255) & ~(size_t)255;
-  const size_t off_f = off_g + (((ghat_elems * sizeof(double2)) + 255) & ~(size_t)255);
+  const size_t ghat_elems = (size_t)units * 4 * ncols * rows;
+  const size_t off_f = (((ghat_elems * sizeof(double2)) + 255) & ~(size_t)255);
   const size_t off_c = off_f + (((size_t)units * 4 * sizeof(double4) + 255) & ~(size_t)255);
   void* ws = nullptr;
   int rc = workspace(st, off_c + 256, &ws);
   if (rc) return rc;
   char* base = static_cast<char*>(ws);
   GradArgs ga;
-  ga.tabs = reinterpret_cast<double2*>(base);
+  ga.tabs = tabs;
   ga.n = n;
+  ga.ncols = ncols;
   ga.c = c;
   ga.nsuper = nsuper;
   ga.s_per = (int)s_per;
   ga.units = units;
   ga.counter = reinterpret_cast<uint32_t*>(base + off_c);
-  ga.ghat = reinterpret_cast<double2*>(base + off_g);
+  ga.ghat = reinterpret_cast<double2*>(base);
   ga.fparts = reinterpret_cast<double4*>(base + off_f);
   ga.plain = o.plain ? 1 : 0;
   hipLaunchKernelGGL(k_reset1, dim3(1), dim3(1), 0, st, ga.counter);
-  hipLaunchKernelGGL(k_grad_prep, dim3((unsigned)batch), dim3(256), 0, st, A, n, rows,
-                     const_cast<double2*>(ga.tabs));
   const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(blocks_full, units));
   void* args[] = {&ga};
   e = hipLaunchKernel(lay.kern, dim3((unsigned)grid), dim3(256), args, lds, st);
   if (e != hipSuccess) return hip_fail(e, "grad sweep launch");
-  hipLaunchKernelGGL(k_grad_finalize, dim3((unsigned)batch), dim3(256), 0, st, ga.ghat, ga.fparts, n, rows,
+  hipLaunchKernelGGL(k_grad_finalize, dim3((unsigned)batch), dim3(256), 0, st, ga.ghat, ga.fparts, n, ncols, rows,
                      (int)s_per, ga.plain, gout, pout, grad);
   e = hipGetLastError();
   return e == hipSuccess ? PH_OK : hip_fail(e, "grad launch");
+}
+
+// Enqueue the gradient of `batch` n x n matrices (device pointers).
+int perm_grad_launch(const double2* A, int n, int64_t batch, const double2* gout, double2* pout, double2* grad,
+                     const Opts& o, hipStream_t st, int cus) {
+  if (batch == 0) return PH_OK;
+  if (n == 1) {
+    hipLaunchKernelGGL(k_grad_n1, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, st, A, batch, gout, pout,
+                       grad);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? PH_OK : hip_fail(e, "grad launch");
+  }
+  const int rows = grad_rows(n);
+  if (rows <= 0) return fail(PH_ERANGE, "no gradient kernel for n=%d", n);
+  // the tables in a workspace slot of their own: the sweep may grow slot 0
+  void* tw = nullptr;
+  int rc = workspace_slot(st, (size_t)batch * n * rows * sizeof(double2), 3, &tw);
+  if (rc) return rc;
+  double2* tabs = static_cast<double2*>(tw);
+  hipLaunchKernelGGL(k_grad_prep, dim3((unsigned)batch), dim3(256), 0, st, A, n, rows, tabs);
+  return grad_sweep(tabs, n, n, batch, gout, pout, grad, o, st, cus);
 }
 
 }  // namespace ph

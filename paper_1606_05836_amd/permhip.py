@@ -265,9 +265,11 @@ def boson_probs(u: torch.Tensor, in_modes, patterns, algo="glynn", accum="dd", u
     return probs
 
 
-def boson_probs_grad(u: torch.Tensor, in_modes, patterns, weights: torch.Tensor | None = None, accum="dd"):
+def boson_probs_grad(u: torch.Tensor, in_modes, patterns, weights: torch.Tensor | None = None, accum="dd",
+                     ungrouped: bool = False):
     """(probs, dU): dU (m x n) holds dL/dU[:, in_modes[k]] in column k for
-    L = sum_p w_p Pr[S -> T_p] (PyTorch's conjugate-Wirtinger convention)."""
+    L = sum_p w_p Pr[S -> T_p] (PyTorch's conjugate-Wirtinger convention).
+    ungrouped: one full sweep per pattern (PH_FLAG_UNGROUPED)."""
     u = _need_square_u(u)
     m = u.shape[0]
     ins, pats = _modes(in_modes, patterns, m)
@@ -279,7 +281,7 @@ def boson_probs_grad(u: torch.Tensor, in_modes, patterns, weights: torch.Tensor 
         w = weights.to(device=u.device, dtype=torch.float64).contiguous()
         if w.numel() != npat:
             raise ValueError("weights needs one entry per pattern")
-    o = opts("glynn", accum)
+    o = opts("glynn", accum, flags=PH_FLAG_UNGROUPED if ungrouped else 0)
     check(lib().ph_boson_probs_grad(_ptr(u), m, u.stride(0), _i32p(ins), n, _i32p(pats), npat, _ptr(w),
                                     _ptr(probs), _ptr(du), du.stride(0), ctypes.byref(o), _stream(u)))
     return probs, du

@@ -67,7 +67,7 @@ def test_argument_errors_are_reported_before_any_device_work(L):
     assert _perm(L, fake, 10, 10, fake, P.PhOpts(7, 0, 0, 0, 0)) == P.PH_EINVAL
     assert _perm(L, fake, 10, 10, fake, P.PhOpts(0, 5, 0, 0, 0)) == P.PH_EINVAL
     assert _perm(L, fake, 10, 10, fake, P.PhOpts(0, 0, 0, 9, 0)) == P.PH_EINVAL
-    assert _perm(L, fake, 10, 10, fake, P.PhOpts(0, 0, 0, 0, 1)) == P.PH_EINVAL
+    assert _perm(L, fake, 10, 10, fake, P.PhOpts(0, 0, 0, 0, 2)) == P.PH_EINVAL  # unknown flag bit
 
 
 def test_python_binding_rejects_non_device_tensors():

@@ -134,6 +134,26 @@ def test_grad_small_against_exact_minors(ph, ins):
     assert np.max(np.abs(pr.cpu().numpy() - ep)) <= 1e-14
 
 
+def test_grouped_gradient_against_exact_minors(ph):
+    # 7..9 photons, at least 5 in single-photon modes: the gradient goes
+    # through the multiplicity-grouped sweeps (and, flagged, full sweeps)
+    m = 14
+    u = I.haar(m, 20)
+    rng = np.random.default_rng(21)
+    cases = [(7, [3, 3, 0, 1, 2, 4, 5]), (8, [0, 0, 1, 1, 2, 3, 4, 5]), (9, [6, 6, 6, 7, 8, 9, 10, 11, 12])]
+    for n, pat in cases:
+        ins = sorted(rng.choice(m, n, replace=False).tolist())
+        pats = np.array([sorted(pat), sorted(rng.choice(m, n, replace=False).tolist())])
+        w = np.array([1.5, -0.25])
+        ex = exact_du(u, ins, pats, w)
+        scale = np.max(np.abs(ex))
+        for ungrouped in (False, True):
+            pr, du = ph.boson_probs_grad(cuda(u), ins, pats, weights=cuda(w), ungrouped=ungrouped)
+            assert np.max(np.abs(du.cpu().numpy() - ex)) <= 1e-12 * scale, (n, ungrouped)
+            ep = np.array([float(O.prob_exact(u, ins, p)) for p in pats])
+            assert np.max(np.abs(pr.cpu().numpy() - ep) / ep) <= 1e-12, (n, ungrouped)
+
+
 def test_grad_single_photon(ph):
     # n = 1: Pr = |U[t, s]|^2, dL/dU[:, s] = 2 w U[t, s] at row t
     m = 5
@@ -243,6 +263,17 @@ def test_full_workload_grouped_against_ungrouped(ph, full_workload):
     u, ins, pats, w, pf, pg, du = full_workload
     pu = ph.boson_probs(cuda(u), ins, pats, ungrouped=True).cpu().numpy()
     assert np.max(np.abs(pu - pf) / pf) <= 2 * PROB_TOL
+
+
+def test_full_workload_gradient_grouped_against_ungrouped(ph, full_workload):
+    u, ins, pats, w, pf, pg, du = full_workload
+    pu, duu = ph.boson_probs_grad(cuda(u), ins, pats, weights=cuda(w), ungrouped=True)
+    duu = duu.cpu().numpy()
+    assert np.max(np.abs(pu.cpu().numpy() - pg) / pg) <= 2 * PROB_TOL
+    # entries of dU are sums of terms of either sign; compare on the scale of
+    # each row
+    scale = np.max(np.abs(duu), axis=1, keepdims=True) + 1e-300
+    assert np.max(np.abs(du - duu) / scale) <= 1e-9
 
 
 def test_full_workload_phase_invariance(ph, full_workload):
