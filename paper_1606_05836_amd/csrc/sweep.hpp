@@ -71,7 +71,7 @@ struct Shape {
   // unrolled block of 2^LOGU steps (chunks with c < LOGU take a plain loop)
   static constexpr int LOGU = NB >= 4 ? 4 : (NB >= 1 ? 1 : 0);
   // number of DPP-resident update columns (register budget)
-  static constexpr int D0 = N <= 32 ? 4 : (N <= 40 ? 3 : (N <= 44 ? 2 : 0));
+  static constexpr int D0 = N <= 40 ? 4 : (N <= 44 ? 2 : 0);
   static_assert(D0 == 0 || N <= DPP_NMAX, "DPP-resident columns need a spill-free kernel");
   static constexpr int D = D0 < LOGU ? D0 : LOGU;
   static constexpr int NP = (2 * N + 15) / 16;  // VGPR pairs per resident column

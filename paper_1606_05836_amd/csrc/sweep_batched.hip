@@ -30,9 +30,9 @@ __device__ __forceinline__ void run_item(const double2* lds, int c, int ncols, c
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nb = ALGO == ALGO_GLYNN ? ncols - 1 : ncols;
   const uint64_t nchunks = (uint64_t)1 << (nb - c);
-  // the item loop keeps extra state live: above n = BATCHED_DPP_NMAX every
-  // column comes from LDS
-  constexpr int DR = N > BATCHED_DPP_NMAX ? 0 : S::D;
+  // the item loop keeps extra state live: above n = 32 at most 3 resident
+  // columns, above n = BATCHED_DPP_NMAX every column comes from LDS
+  constexpr int DR = N > BATCHED_DPP_NMAX ? 0 : (N > 32 && S::D > 3 ? 3 : S::D);
   Resident<N, ALGO, DR> res;
   res.load(lds);
   dd2 acc = {0.0, 0.0, 0.0, 0.0};
