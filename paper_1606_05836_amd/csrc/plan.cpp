@@ -159,17 +159,24 @@ static void save_cache_locked() {
 int plan_build(const int32_t* n_host, const int64_t* off_host, int64_t batch, const Opts& o, const int32_t* c_force,
                hipStream_t st, PlanImpl** out, const int32_t* ncols_host = nullptr);
 
+// Terms one tuning run may sweep: candidates are timed on synthetic batches
+// of about this many terms.  Orders with more terms per matrix than this are
+// not timed (a run would be a whole permanent per candidate, seconds to
+// hours); they take the default length, whose seed work is well under 1% of
+// the sweep at that size.
+constexpr int TUNE_LOG2_TERMS = 27;
+
 // Time the batched sweep for each candidate chunk length on a synthetic batch
 // of order-n matrices (about 2^27 terms) and keep the fastest.
 static int tune_chunk(int n, int algo, bool plain, hipStream_t st, int* c_out) {
   int lo, hi;
   chunk_range(n, algo, &lo, &hi);
-  if (lo == hi) {
-    *c_out = lo;
+  const int nb = gray_bits(n, algo);
+  if (lo == hi || nb > TUNE_LOG2_TERMS) {
+    *c_out = default_chunk(n, algo);
     return PH_OK;
   }
-  const int nb = gray_bits(n, algo);
-  const int64_t copies = nb >= 27 ? 1 : ((int64_t)1 << std::min(27 - nb, 14));
+  const int64_t copies = (int64_t)1 << std::min(TUNE_LOG2_TERMS - nb, 14);
   const int64_t elems = copies * n * n;
   double2* a = nullptr;
   double2* out = nullptr;

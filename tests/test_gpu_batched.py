@@ -1,4 +1,7 @@
 """Batched permanents (plans, hipGraph replay) against the exact oracle."""
+import math
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -119,3 +122,24 @@ def test_perm_of_leading_batch_dims(ph):
         for j in range(3):
             assert O.rel_err(complex(got[i, j]), O.perm_exact(a[i, j])) <= 1e-12
     assert ph.perm(torch.zeros((0, 4, 4), dtype=torch.complex128, device="cuda")).shape == (0,)
+
+
+def test_larger_size_buckets_exact(ph):
+    # the batched kernels for 33..40 (three resident columns) and 41..44 (two)
+    # on inputs with exact answers: diag(1+i) gives (1+i)^n, a row-scaled
+    # diagonal gives the product of its entries, all-ones n!
+    mats = [I.diag_matrix(33, 1 + 1j), np.ones((34, 34), np.complex128), I.diag_matrix(41, 1 + 1j)]
+    d = np.diag(np.linspace(0.5, 1.5, 36)).astype(np.complex128)
+    d[3, 3] = 2.0 - 1.0j
+    mats.append(d)
+    got = ph.perm_batched([torch.from_numpy(m).to("cuda") for m in mats]).cpu().numpy()
+    assert complex(got[0]) == (1 + 1j) ** 33
+    assert abs(complex(got[1]) - math.factorial(34)) <= 1e-10 * math.factorial(34)
+    assert complex(got[2]) == (1 + 1j) ** 41
+    # the permanent of a diagonal matrix is the product of its diagonal
+    re, im = Fraction(1), Fraction(0)
+    for z in np.diag(d):
+        zr, zi = Fraction(z.real), Fraction(z.imag)
+        re, im = re * zr - im * zi, re * zi + im * zr
+    want = complex(float(re), float(im))
+    assert abs(complex(got[3]) - want) <= 1e-14 * abs(want)

@@ -173,6 +173,13 @@ def test_diag_one_plus_i_exact(ph):
             assert run(ph, I.diag_matrix(n, 1 + 1j), algo=algo) == want
 
 
+def test_diag_one_plus_i_exact_n41(ph):
+    """The single-matrix kernels for n = 41..44 (two resident columns):
+    2^40 terms, each exactly (1+i)^41."""
+    want = complex(*[float(x) for x in _allr_exact_pow(41)])
+    assert run(ph, I.diag_matrix(41, 1 + 1j)) == want
+
+
 def _allr_exact_pow(n):
     re, im = 1, 0
     for _ in range(n):
