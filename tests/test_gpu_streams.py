@@ -1,0 +1,67 @@
+"""The library's per-stream state (workspace, plan cache, pinned staging):
+every entry point gives the same bits on a side stream as on the default
+stream, and work queued on two streams at once does not mix."""
+import numpy as np
+import pytest
+
+import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ph():
+    import paper_1606_05836_amd as ph
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return ph
+
+
+def cuda(a):
+    return torch.from_numpy(np.array(a, copy=True)).to("cuda")
+
+
+def run_all(ph, a, b, u, ins, pats):
+    return (ph.perm(a), ph.perm_batched(b), ph.perm_grad(b[:4])[1], ph.boson_probs(u, ins, pats),
+            ph.boson_probs_grad(u, ins, pats)[1])
+
+
+def test_side_stream_gives_the_same_bits(ph):
+    a = cuda(I.config3_matrix(24))
+    b = cuda(I.config4_batch(32, 16))
+    u_np, ins, pats = I.config5_workload(m=200, n=16, patterns=6)
+    u = cuda(u_np)
+    ref = [x.cpu() for x in run_all(ph, a, b, u, ins, pats)]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        got = run_all(ph, a, b, u, ins, pats)
+    side.synchronize()
+    for r, g in zip(ref, got):
+        assert torch.equal(r, g.cpu())
+
+
+def test_two_streams_in_flight(ph):
+    # different work on two streams at once, each checked against its own
+    # default-stream result
+    m1 = cuda(I.config4_batch(64, 18))
+    m2 = cuda(I.config3_matrix(26))
+    r1 = ph.perm_batched(m1).cpu()
+    r2 = ph.perm(m2).cpu()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    s2.wait_stream(torch.cuda.current_stream())
+    outs = []
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            o1 = ph.perm_batched(m1)
+        with torch.cuda.stream(s2):
+            o2 = ph.perm(m2)
+        outs.append((o1, o2))
+    s1.synchronize()
+    s2.synchronize()
+    for o1, o2 in outs:
+        assert torch.equal(o1.cpu(), r1)
+        assert torch.equal(o2.cpu(), r2)
