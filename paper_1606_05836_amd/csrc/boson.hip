@@ -386,62 +386,74 @@ static void plan_sweeps(const int32_t* patterns, int n, int64_t npat, bool ungro
   sw->pv[npat] = (int32_t)sw->w.size();
 }
 
-// Eq. (1) permanents of all patterns through the grouped sweeps into perms
-// (device, npat complex).  in_dev: the input modes already on the device.
-static int boson_perms_grouped(hipStream_t st, const ph_c128* U, int64_t ldu, const int32_t* in_modes, int n,
-                               const int32_t* patterns, int64_t npat, const Opts& o, double2* perms) {
+// Eq. (1) probabilities of all patterns through the grouped sweeps: one
+// staged upload of the mode lists and sweep descriptions, the sweep tables,
+// one batched plan replay, the weighted combination and the normalisation.
+static int boson_probs_grouped(hipStream_t st, const ph_c128* U, int64_t ldu, const int32_t* in_modes, int n,
+                               const int32_t* patterns, int64_t npat, const Opts& o, double* probs) {
   Sweeps sw;
   plan_sweeps(patterns, n, npat, o.ungrouped, &sw);
   const int64_t V = (int64_t)sw.w.size();
   std::vector<int32_t> ns(V, n);
-  // device layout in workspace slot 2: in_modes | vcol | vncols | vcoef | vncoef |
-  // colmodes | collmodes | pv | coefs | w | tab_off | vout
+  // device layout in workspace slot 2 (the first NP_UP entries are uploaded)
+  enum { P_IN, P_VCOL, P_VNCOLS, P_VCOEF, P_VNCOEF, P_COLM, P_COLLM, P_PV, P_PAT, P_COEFS, P_W, P_TABOFF, NP_UP,
+         B_VOUT = NP_UP, B_PERMS, NB_ALL };
   auto one = [](size_t x) { return std::max<size_t>(x, 1); };
-  const size_t sz[12] = {one(n) * 4,        one(V) * 4,          one(V) * 4,
-                         one(V) * 4,        one(V) * 4,          one(sw.colmodes.size()) * 4,
-                         one(sw.collmodes.size()) * 4, one(npat + 1) * 4, one(sw.coefs.size()) * 8,
-                         one(V) * 8,        one(V) * 8,          one(V) * 16};
-  size_t off[13];
+  size_t sz[NB_ALL];
+  sz[P_IN] = one(n) * 4;
+  sz[P_VCOL] = sz[P_VNCOLS] = sz[P_VCOEF] = sz[P_VNCOEF] = one(V) * 4;
+  sz[P_COLM] = one(sw.colmodes.size()) * 4;
+  sz[P_COLLM] = one(sw.collmodes.size()) * 4;
+  sz[P_PV] = one(npat + 1) * 4;
+  sz[P_PAT] = one(npat * n) * 4;
+  sz[P_COEFS] = one(sw.coefs.size()) * 8;
+  sz[P_W] = sz[P_TABOFF] = one(V) * 8;
+  sz[B_VOUT] = one(V) * 16;
+  sz[B_PERMS] = one(npat) * 16;
+  size_t off[NB_ALL + 1];
   off[0] = 0;
-  for (int q = 0; q < 12; ++q) off[q + 1] = off[q] + up256(sz[q]);
+  for (int q = 0; q < NB_ALL; ++q) off[q + 1] = off[q] + up256(sz[q]);
   void* ws = nullptr;
-  int rc = workspace_slot(st, off[12], 2, &ws);
+  int rc = workspace_slot(st, off[NB_ALL], 2, &ws);
   if (rc) return rc;
   char* d = static_cast<char*>(ws);
   auto I32 = [&](int q) { return reinterpret_cast<int32_t*>(d + off[q]); };
-  double* d_coefs = reinterpret_cast<double*>(d + off[8]);
-  double* d_w = reinterpret_cast<double*>(d + off[9]);
-  int64_t* d_taboff = reinterpret_cast<int64_t*>(d + off[10]);
-  double2* vout = reinterpret_cast<double2*>(d + off[11]);
+  auto F64 = [&](int q) { return reinterpret_cast<double*>(d + off[q]); };
+  auto C128 = [&](int q) { return reinterpret_cast<double2*>(d + off[q]); };
   auto fill = [&](PlanImpl* p) -> int {
     const std::vector<int64_t>& toff = plan_table_offsets(p);
-    const Piece pc[11] = {{in_modes, (size_t)n * 4},
-                          {sw.vcol.data(), (size_t)V * 4},
-                          {sw.vncols.data(), (size_t)V * 4},
-                          {sw.vcoef.data(), (size_t)V * 4},
-                          {sw.vncoef.data(), (size_t)V * 4},
-                          {sw.colmodes.data(), sw.colmodes.size() * 4},
-                          {sw.collmodes.data(), sw.collmodes.size() * 4},
-                          {sw.pv.data(), (size_t)(npat + 1) * 4},
-                          {sw.coefs.data(), sw.coefs.size() * 8},
-                          {sw.w.data(), (size_t)V * 8},
-                          {toff.data(), (size_t)V * 8}};
-    int r = upload_at(st, d, off, pc, 11);
+    const Piece pc[NP_UP] = {{in_modes, (size_t)n * 4},
+                             {sw.vcol.data(), (size_t)V * 4},
+                             {sw.vncols.data(), (size_t)V * 4},
+                             {sw.vcoef.data(), (size_t)V * 4},
+                             {sw.vncoef.data(), (size_t)V * 4},
+                             {sw.colmodes.data(), sw.colmodes.size() * 4},
+                             {sw.collmodes.data(), sw.collmodes.size() * 4},
+                             {sw.pv.data(), (size_t)(npat + 1) * 4},
+                             {patterns, (size_t)(npat * n) * 4},
+                             {sw.coefs.data(), sw.coefs.size() * 8},
+                             {sw.w.data(), (size_t)V * 8},
+                             {toff.data(), (size_t)V * 8}};
+    int r = upload_at(st, d, off, pc, NP_UP);
     if (r) return r;
     hipLaunchKernelGGL(k_boson_vtab, dim3((unsigned)V), dim3(256), 0, st, reinterpret_cast<const double2*>(U), ldu,
-                       I32(0), n, I32(1), I32(2), I32(3), I32(4), I32(5), I32(6), d_coefs, d_taboff,
+                       I32(P_IN), n, I32(P_VCOL), I32(P_VNCOLS), I32(P_VCOEF), I32(P_VNCOEF), I32(P_COLM),
+                       I32(P_COLLM), F64(P_COEFS), reinterpret_cast<int64_t*>(d + off[P_TABOFF]),
                        plan_tables_base(p));
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? PH_OK : hip_fail(e, "boson table launch");
   };
   Opts og = o;
   og.algo = PH_GLYNN;
-  rc = plan_ext_run(ns.data(), sw.vncols.data(), V, og, st, fill, vout);
+  rc = plan_ext_run(ns.data(), sw.vncols.data(), V, og, st, fill, C128(B_VOUT));
   if (rc) return rc;
-  hipLaunchKernelGGL(k_boson_combine, dim3((unsigned)((npat + 255) / 256)), dim3(256), 0, st, vout,
-                     (const int32_t*)nullptr, d_w, I32(7), npat, o.plain ? 1 : 0, perms);
+  const unsigned pb = (unsigned)((npat + 255) / 256);
+  hipLaunchKernelGGL(k_boson_combine, dim3(pb), dim3(256), 0, st, C128(B_VOUT), (const int32_t*)nullptr, F64(P_W),
+                     I32(P_PV), npat, o.plain ? 1 : 0, C128(B_PERMS));
+  hipLaunchKernelGGL(k_boson_normalize, dim3(pb), dim3(256), 0, st, C128(B_PERMS), I32(P_IN), I32(P_PAT), n, npat,
+                     (const double*)nullptr, probs, (double2*)nullptr);
   const hipError_t e = hipGetLastError();
-  return e == hipSuccess ? PH_OK : hip_fail(e, "boson combine launch");
+  return e == hipSuccess ? PH_OK : hip_fail(e, "boson launch");
 }
 
 // ------------------------------------------- gradient of the grouped sweeps
@@ -694,15 +706,13 @@ extern "C" int ph_boson_probs(const ph_c128* U, int32_t m, int64_t ldu, const in
   if (n_patterns == 0) return PH_OK;
   if (num_cus() <= 0) return PH_EUNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
+  if (n >= GROUP_MIN_SINGLES + 1 && o.algo == PH_GLYNN)
+    return boson_probs_grouped(st, U, ldu, in_modes, n, patterns, n_patterns, o, probs);
   BosonBufs b;
   if ((rc = boson_setup(st, U, m, ldu, in_modes, n, patterns, n_patterns, false, &b))) return rc;
-  if (n >= GROUP_MIN_SINGLES + 1 && o.algo == PH_GLYNN) {
-    rc = boson_perms_grouped(st, U, ldu, in_modes, n, patterns, n_patterns, o, b.perms);
-  } else {
-    std::vector<int32_t> ns(n_patterns, n);
-    rc = ph_perm_batched(reinterpret_cast<const ph_c128*>(b.a), nullptr, ns.data(), n_patterns,
-                         reinterpret_cast<ph_c128*>(b.perms), opt, stream);
-  }
+  std::vector<int32_t> ns(n_patterns, n);
+  rc = ph_perm_batched(reinterpret_cast<const ph_c128*>(b.a), nullptr, ns.data(), n_patterns,
+                       reinterpret_cast<ph_c128*>(b.perms), opt, stream);
   if (rc) return rc;
   hipLaunchKernelGGL(k_boson_normalize, dim3((unsigned)((n_patterns + 255) / 256)), dim3(256), 0, st, b.perms,
                      b.d_in, b.d_pat, n, n_patterns, (const double*)nullptr, probs, (double2*)nullptr);
