@@ -515,7 +515,10 @@ int grad_sweep(const double2* tabs, int n, int ncols, int64_t batch, const doubl
   if (!lay.kern) return fail(PH_ERANGE, "no gradient kernel for n=%d", n);
   const int K = lay.K, rows = lay.H * lay.M, ng = 64 / lay.H, nb = ncols - 1;
   if (nb < K) return fail(PH_EINVAL, "gradient sweep over %d columns of %d rows", ncols, n);
-  int c = o.chunk_log2 > 0 ? o.chunk_log2 : std::min(10, nb - 4);
+  // chunk length: at most 2^10 terms, and at least one chunk for each group of
+  // the four wavefronts of a unit (4 * ng chunks) where the sweep is long enough
+  const int need = 2 + (ng == 8 ? 3 : 4);
+  int c = o.chunk_log2 > 0 ? o.chunk_log2 : std::min(10, nb - need);
   c = std::max(K, std::min(c, nb));  // K >= LOGP, so a chunk holds whole runs
   const int64_t nsuper = (int64_t)((((uint64_t)1 << (nb - c)) + ng - 1) / ng);
   const size_t lds = (size_t)ncols * rows * sizeof(double2) + 4 * 64 * (size_t)(lay.M | 1) * sizeof(double2);

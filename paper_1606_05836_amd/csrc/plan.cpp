@@ -402,9 +402,10 @@ int plan_build(const int32_t* n_host, const int64_t* off_host, int64_t batch, co
     }
     p->c[b] = it->second;
     if (p->ncols[b] != n) {
-      // fewer columns: keep at least 64 chunks (one per lane) where possible
+      // fewer columns: keep at least 256 chunks (one per lane of the four
+      // wavefronts of a workgroup) where possible
       const int nb = gray_bits(p->ncols[b], o.algo);
-      p->c[b] = std::max(min_chunk_log2(nb), std::min(p->c[b], std::max(min_chunk_log2(nb), nb - 6)));
+      p->c[b] = std::max(min_chunk_log2(nb), std::min(p->c[b], std::max(min_chunk_log2(nb), nb - 8)));
     }
   }
   // order: bucket (largest first), then n descending, then batch index
