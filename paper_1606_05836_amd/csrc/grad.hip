@@ -68,16 +68,27 @@ constexpr int DPP_QUAD_XOR1 = 0xB1, DPP_QUAD_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x14
 // Stored columns (K) and target wavefronts per SIMD per (rows per lane M,
 // lanes per term H).
 #ifndef PH_GRAD_K
-#define PH_GRAD_K(M, H) ((H) == 8 ? ((M) <= 2 ? 4 : 3) : ((M) == 1 ? 1 : ((M) <= 5 ? 2 : 1)))
+#define PH_GRAD_K(M, H) ((H) == 8 ? ((M) <= 2 ? 4 : 3) : ((M) == 1 ? 1 : ((M) <= 4 ? 2 : 3)))
 #endif
 #ifndef PH_GRAD_WAVES
 #define PH_GRAD_WAVES(M, H) ((H) == 8 ? ((M) <= 2 ? 3 : 2) : ((M) <= 1 ? 4 : ((M) <= 3 ? 3 : 2)))
 #endif
-// smallest n that uses H = 8 lanes per term
-#ifndef PH_GRAD_H8_MIN
-#define PH_GRAD_H8_MIN 9
+// which orders split a term over 4 lanes (the others over 8); the 4-lane
+// layouts with 3 and 4 rows per lane are compiled only if some order uses them
+#ifndef PH_GRAD_USE_H4
+#define PH_GRAD_USE_H4(n) ((n) <= 8 || ((n) >= 17 && (n) <= 20))
+#endif
+#ifndef PH_GRAD_H4_M3
+#define PH_GRAD_H4_M3 0
+#endif
+#ifndef PH_GRAD_H4_M4
+#define PH_GRAD_H4_M4 0
 #endif
 
+// stored columns kept in registers (default: all K)
+#ifndef PH_GRAD_KR
+#define PH_GRAD_KR(M, H) ((H) == 4 && (M) == 5 ? 2 : 8)
+#endif
 // log2 of the terms per loop iteration (bits below it flip without a branch)
 #ifndef PH_GRAD_LOGP
 #define PH_GRAD_LOGP(M, H) ((M) == 3 && (H) == 8 ? 2 : 1)
@@ -96,6 +107,10 @@ struct GradShape {
   static constexpr int WAVES = PH_GRAD_WAVES(M, H);
   // terms per loop iteration: 2^LOGP (LOGP <= K)
   static constexpr int LOGP = PH_GRAD_LOGP(M, H) < K ? PH_GRAD_LOGP(M, H) : K;
+  // stored columns also held in registers (the rest are read from LDS when
+  // they flip): at least the LOGP columns of the straight-line steps
+  static constexpr int KR0 = PH_GRAD_KR(M, H) < K ? PH_GRAD_KR(M, H) : K;
+  static constexpr int KR = KR0 > LOGP ? KR0 : LOGP;
   // LDS staging: lane l writes its M complex values at complex offset l * SS,
   // SS = M rounded up to odd, so the 16-byte writes of eight consecutive
   // lanes cover all 32 banks once and the reads are conflict-free
@@ -120,7 +135,7 @@ struct GradLane {
   double2 r[M];
   double2 W[M];
   double2 G[GradShape<M, H>::K][M];
-  double2 colK[GradShape<M, H>::K][M];  // the lane's rows of columns 1..K
+  double2 colK[GradShape<M, H>::KR][M];  // the lane's rows of columns 1..KR
 };
 
 // Sum of wt * W over the groups of the wavefront, through LDS.  Lane
@@ -264,7 +279,7 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
 #pragma unroll
       for (int ii = 0; ii < M; ++ii) {
         L.G[b][ii] = make_double2(0.0, 0.0);
-        L.colK[b][ii] = tab[(b + 1) * ROWS + row0 + ii];
+        if (b < GS::KR) L.colK[b < GS::KR ? b : 0][ii] = tab[(b + 1) * ROWS + row0 + ii];
       }
     dd2 acc = {0.0, 0.0, 0.0, 0.0};
     double bacc[GS::R];
@@ -313,7 +328,10 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
                   L.G[bb][ii].x = fma(2.0 * sgu, L.W[ii].x, L.G[bb][ii].x);
                   L.G[bb][ii].y = fma(2.0 * sgu, L.W[ii].y, L.G[bb][ii].y);
                 }
-                grad_apply<M, H>(L, sgu, L.colK[bb]);
+                if constexpr (bb < GS::KR)
+                  grad_apply<M, H>(L, sgu, L.colK[bb]);
+                else
+                  grad_update<M, H>(L, sgu, tab + (bb + 1) * ROWS + row0);
               }
             });
           } else {
@@ -466,7 +484,7 @@ static GradLayout layout() {
 }
 
 static GradLayout grad_layout(int n) {
-  if (n >= PH_GRAD_H8_MIN) {
+  if (!PH_GRAD_USE_H4(n)) {
     switch ((n + 7) / 8) {
       case 2: return layout<2, 8>();
       case 3: return layout<3, 8>();
@@ -477,24 +495,13 @@ static GradLayout grad_layout(int n) {
   switch ((n + 3) / 4) {
     case 1: return layout<1, 4>();
     case 2: return layout<2, 4>();
-#if PH_GRAD_H8_MIN > 9
+#if PH_GRAD_H4_M3
     case 3: return layout<3, 4>();
 #endif
-#if PH_GRAD_H8_MIN > 13
+#if PH_GRAD_H4_M4
     case 4: return layout<4, 4>();
 #endif
-#if PH_GRAD_H8_MIN > 17
     case 5: return layout<5, 4>();
-#endif
-#if PH_GRAD_H8_MIN > 21
-    case 6: return layout<6, 4>();
-#endif
-#if PH_GRAD_H8_MIN > 25
-    case 7: return layout<7, 4>();
-#endif
-#if PH_GRAD_H8_MIN > 29
-    case 8: return layout<8, 4>();
-#endif
   }
   return GradLayout{0, 0, 0, nullptr};
 }
