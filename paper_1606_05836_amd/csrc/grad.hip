@@ -68,7 +68,7 @@ constexpr int DPP_QUAD_XOR1 = 0xB1, DPP_QUAD_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x14
 // Stored columns (K) and target wavefronts per SIMD per (rows per lane M,
 // lanes per term H).
 #ifndef PH_GRAD_K
-#define PH_GRAD_K(M, H) ((H) == 8 ? ((M) <= 2 ? 4 : 3) : ((M) == 1 ? 1 : ((M) <= 4 ? 2 : 3)))
+#define PH_GRAD_K(M, H) ((H) == 8 ? 4 : ((M) == 1 ? 1 : ((M) <= 4 ? 2 : 3)))
 #endif
 #ifndef PH_GRAD_WAVES
 #define PH_GRAD_WAVES(M, H) ((H) == 8 ? ((M) <= 2 ? 3 : 2) : ((M) <= 1 ? 4 : ((M) <= 3 ? 3 : 2)))
@@ -87,7 +87,7 @@ constexpr int DPP_QUAD_XOR1 = 0xB1, DPP_QUAD_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x14
 
 // stored columns kept in registers (default: all K)
 #ifndef PH_GRAD_KR
-#define PH_GRAD_KR(M, H) ((H) == 4 && (M) == 5 ? 2 : 8)
+#define PH_GRAD_KR(M, H) ((H) == 8 ? ((M) >= 3 ? 3 : 8) : ((M) == 5 ? 2 : 8))
 #endif
 // log2 of the terms per loop iteration (bits below it flip without a branch)
 #ifndef PH_GRAD_LOGP
