@@ -173,6 +173,32 @@ def extras(ph, dev, stream):
     return res
 
 
+def grad_ratio(ph, dev, stream, ns):
+    """Gradient cost against the forward, per order n: about 2^29 terms per
+    call (batch max(8, 2^(30-n)) matrices of n rows of Haar(400, 41)), both
+    timed with HIP events; the gradient is also checked by Laplace expansion
+    along every row, sum_j a_ij dPer/da_ij = Per."""
+    import torch
+
+    import inputs
+
+    res = {}
+    for n in ns:
+        batch = max(8, 1 << max(0, 30 - n))
+        a = torch.from_numpy(inputs.config4_batch(batch, n)).to(dev)
+        reps = 2 if n >= 30 else 3
+        ph.perm_batched(a)
+        fwd = _median(_event_ms(lambda: ph.perm_batched(a), reps, stream))
+        p, g = ph.perm_grad(a)
+        grad = _median(_event_ms(lambda: ph.perm_grad(a), reps, stream))
+        lap = ((a * torch.conj(g)).sum(dim=2) - p.unsqueeze(1)).abs() / p.abs().unsqueeze(1)
+        res[n] = {"batch": batch, "fwd_ms": fwd, "grad_ms": grad, "ratio": grad / fwd,
+                  "laplace_max_rel": float(lap.max())}
+        _log(f"grad ratio n={n}: batch {batch}, fwd {fwd:.2f} ms, grad {grad:.2f} ms, ratio {grad / fwd:.2f}, "
+             f"laplace {float(lap.max()):.1e}")
+    return res
+
+
 def _stored_exact():
     """Exact permanents committed under tests/golden (written by the oracle):
     name -> (n, sha256 of the input bytes, complex value)."""
@@ -299,6 +325,8 @@ def main():
                     help="run one plain device copy of this size first (counter calibration)")
     ap.add_argument("--precision", default="", metavar="N,N",
                     help="print only the precision study, with these large sizes (e.g. 40,44)")
+    ap.add_argument("--grad-ratio", default="", metavar="N,N",
+                    help="print only the gradient/forward cost ratio at these orders")
     ap.add_argument("--precision-allr", action="store_true",
                     help="print only the precision study on the paper's all-r matrices")
     args = ap.parse_args()
@@ -322,6 +350,10 @@ def main():
     kw = dict(accum=args.accum, chunk_log2=args.chunk_log2, waves=args.waves)
     if args.precision_allr:
         print(json.dumps({"precision_allr": precision_allr(ph, dev)}), flush=True)
+        return
+    if args.grad_ratio:
+        ns = [int(x) for x in args.grad_ratio.split(",") if x.strip()]
+        print(json.dumps({"grad_ratio": grad_ratio(ph, dev, stream, ns)}), flush=True)
         return
     if args.precision:
         large = [int(x) for x in args.precision.split(",") if x.strip() and int(x) > 0]

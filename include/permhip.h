@@ -90,6 +90,38 @@ enum {
  * chunks, one per GPU lane at a time; see the formulas above. */
 int ph_perm(const ph_c128* A, int32_t n, int64_t lda, ph_c128* out, const ph_opts* opt, void* stream);
 
+/* One share of a permanent's Gray-code sum, for sums split across devices or
+ * run as resumable segments.  The parallel listings of the Supplementary
+ * (Algorithms S1 and S2) give each process a contiguous range of the term
+ * index k and reduce the partial sums at the end; these three calls are that
+ * split.
+ *
+ * ph_perm_chunk_log2: *out (host) receives c, the log2 chunk length that
+ * ph_perm and ph_perm_partial use for this n and these options.
+ *
+ * ph_perm_partial: the sum over terms k in [k_begin, k_end) of Eq. (S2)
+ * (2^(n-1) terms in all) or Eq. (S1) (2^n), each term with its sign, before
+ * the formula's scale (no 2^-(n-1), no (-1)^n).  Term k is the summand of
+ * the Gray word w = k XOR (k >> 1): BB/FG takes delta_0 = +1 and
+ * delta_{b+1} = -1 iff bit b of w is set; Ryser puts column b in S iff bit b
+ * of w is set.  k_begin and k_end are multiples of 2^c, with
+ * k_begin <= k_end <= the term count; an empty range gives 0.
+ * partial (device) receives 4 doubles {re_hi, re_lo, im_hi, im_lo}:
+ * a double-double per component (PH_ACC_PLAIN: the lo halves are 0).  A, n,
+ * lda as ph_perm, 1 <= n <= PH_NMAX.  The result is deterministic for the
+ * same inputs, range, options and device; the split of a range into shares
+ * changes the rounding of the total, not its exactness bound.
+ *
+ * ph_perm_combine: out (device, one complex128) = the scaled sum of `count`
+ * partials (device, 4 doubles each) added in index order, with the same
+ * n and options (algo, accum) as the calls that made them.  Partials covering
+ * the whole range [0, term count) give Per(A). */
+int ph_perm_chunk_log2(int32_t n, const ph_opts* opt, int32_t* out);
+int ph_perm_partial(const ph_c128* A, int32_t n, int64_t lda, uint64_t k_begin, uint64_t k_end, double* partial,
+                    const ph_opts* opt, void* stream);
+int ph_perm_combine(const double* partials, int64_t count, int32_t n, ph_c128* out, const ph_opts* opt,
+                    void* stream);
+
 /* Batched permanents in one launch sequence.  Matrix b is n_host[b] x
  * n_host[b], row-major and contiguous (lda = n), starting at
  * A_packed + offsets_host[b] (elements); offsets_host = NULL means the

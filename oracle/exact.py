@@ -154,6 +154,33 @@ def ryser_subsets_int(g):
     return re, im
 
 
+def ryser_gray_raw(g, k_begin: int = 0, k_end: int | None = None):
+    """Eq. (S1) before its (-1)^n factor, over the Gray indices k in
+    [k_begin, k_end) of a Gaussian-integer matrix: the subset of index k is
+    S = {columns b : bit b of gray(k) is set}, and its term
+    (-1)^|S| prod_i sum_{j in S} g_ij is formed from scratch.  Returns the
+    exact partial sum as ints (the empty set contributes 0 for n >= 1)."""
+    n = len(g)
+    total = 1 << n
+    if k_end is None:
+        k_end = total
+    if not 0 <= k_begin <= k_end <= total:
+        raise ValueError("Gray range out of bounds")
+    re = im = 0
+    for k in range(k_begin, k_end):
+        word = gray(k)
+        cols = [j for j in range(n) if (word >> j) & 1]
+        rowsums = [(sum(g[i][j][0] for j in cols), sum(g[i][j][1] for j in cols)) for i in range(n)]
+        p = _prod(rowsums)
+        if len(cols) % 2:
+            re -= p[0]
+            im -= p[1]
+        else:
+            re += p[0]
+            im += p[1]
+    return re, im
+
+
 # ------------------------------------------------------------ Glynn, Eq. (S2)
 
 

@@ -12,7 +12,12 @@ from .permhip import (  # noqa: F401
     lib,
     perm,
     perm_batched,
+    perm_chunk_log2,
+    perm_combine,
+    perm_partial,
+    gray_terms,
     perm_grad,
     version,
 )
+from . import segments  # noqa: F401
 from .autograd import BosonProbsFn, PermFn, boson_probabilities, permanent  # noqa: F401

@@ -36,10 +36,8 @@ __global__ void k_reset(uint32_t* __restrict__ counters, int count) {
 
 // Fixed-order reduction of partials [begin, end) by one block: thread t sums a
 // contiguous slice in order, then thread 0 sums the slice totals in order.
-// Then the formula's scale: 2^-(n-1) (BB/FG, exact on both halves of the
-// double-double) or (-1)^n (Ryser), and a single rounding to complex128.
-__device__ void finalize_range(const double4* __restrict__ p, int64_t begin, int64_t end, int n, int algo,
-                               int plain, double2* __restrict__ out) {
+// The total is valid in thread 0 only.
+__device__ dd2 reduce_range(const double4* __restrict__ p, int64_t begin, int64_t end, int plain) {
   __shared__ dd2 part[256];
   const int t = threadIdx.x, nt = blockDim.x;
   const int64_t cnt = end - begin;
@@ -56,8 +54,8 @@ __device__ void finalize_range(const double4* __restrict__ p, int64_t begin, int
   }
   part[t] = acc;
   __syncthreads();
+  dd2 s = part[0];
   if (t == 0) {
-    dd2 s = part[0];
     for (int q = 1; q < nt; ++q) {
       if (plain) {
         s.hr += part[q].hr;
@@ -66,6 +64,17 @@ __device__ void finalize_range(const double4* __restrict__ p, int64_t begin, int
         s = dd_add(s, part[q]);
       }
     }
+  }
+  return s;
+}
+
+// The reduced sum, then the formula's scale: 2^-(n-1) (BB/FG, exact on both
+// halves of the double-double) or (-1)^n (Ryser), and a single rounding to
+// complex128.
+__device__ void finalize_range(const double4* __restrict__ p, int64_t begin, int64_t end, int n, int algo,
+                               int plain, double2* __restrict__ out) {
+  const dd2 s = reduce_range(p, begin, end, plain);
+  if (threadIdx.x == 0) {
     double2 r;
     if (n == 0) {
       r = make_double2(1.0, 0.0);  // permanent of the empty matrix
@@ -86,6 +95,14 @@ __global__ void k_finalize_single(const double4* __restrict__ p, int64_t nparts,
   finalize_range(p, 0, nparts, n, algo, plain, out);
 }
 
+// One unscaled double-double {re_hi, re_lo, im_hi, im_lo} from the per-wave
+// partials of a share of the Gray-code range.
+__global__ void k_reduce_partials(const double4* __restrict__ p, int64_t nparts, int plain,
+                                  double4* __restrict__ out) {
+  const dd2 s = reduce_range(p, 0, nparts, plain);
+  if (threadIdx.x == 0) *out = make_double4(s.hr, s.lr, s.hi, s.li);
+}
+
 __global__ void k_finalize_batched(const MatDesc* __restrict__ mats, const double4* __restrict__ p, int algo,
                                    int plain, double2* __restrict__ out) {
   const MatDesc m = mats[blockIdx.x];
@@ -101,6 +118,10 @@ void launch_prep(const double2* a, int64_t lda, int n, int algo, double2* tab, h
 void launch_finalize_single(const double4* partials, int64_t nparts, int n, int algo, int plain, double2* out,
                             hipStream_t st) {
   hipLaunchKernelGGL(k_finalize_single, dim3(1), dim3(256), 0, st, partials, nparts, n, algo, plain, out);
+}
+
+void launch_reduce_partials(const double4* partials, int64_t nparts, int plain, double4* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, st, partials, nparts, plain, out);
 }
 
 // Deterministic bounded values for timing runs (no meaning beyond that).

@@ -175,16 +175,12 @@ extern "C" int ph_perm(const ph_c128* A, int32_t n, int64_t lda, ph_c128* out, c
 
 namespace ph {
 
-int perm_single(const double2* A, int n, int64_t lda, double2* out, const Opts& o, hipStream_t st, int cus) {
+// Sweep the chunks [chunk0, chunk0 + nchunks) of length 2^c of one matrix:
+// the table is staged from A into the workspace, then one partial per wave is
+// written to the workspace; *parts and *nparts describe them.
+static int sweep_share(const double2* A, int n, int64_t lda, int c, uint64_t chunk0, uint64_t nchunks,
+                       const Opts& o, hipStream_t st, int cus, double4** parts, int64_t* nparts) {
   hipError_t e;
-  if (n == 0) {
-    launch_finalize_single(nullptr, 0, 0, o.algo, o.plain, out, st);
-    e = hipGetLastError();
-    return e == hipSuccess ? PH_OK : hip_fail(e, "finalize launch");
-  }
-  const int nb = gray_bits(n, o.algo);
-  const int c = pick_chunk_log2(n, o.algo, o.chunk_log2);
-  const uint64_t nchunks = (uint64_t)1 << (nb - c);
   const uint64_t nsuper = (nchunks + 63) / 64;
   const void* kern = single_kernel(n, o.algo);
   if (!kern) return fail(PH_ERANGE, "no kernel for n=%d", n);
@@ -204,15 +200,33 @@ int perm_single(const double2* A, int n, int64_t lda, double2* out, const Opts& 
   int rc = workspace(st, part_off + nwaves * sizeof(double4), &ws);
   if (rc) return rc;
   double2* tab = reinterpret_cast<double2*>(ws);
-  double4* parts = reinterpret_cast<double4*>(reinterpret_cast<char*>(ws) + part_off);
+  double4* pw = reinterpret_cast<double4*>(reinterpret_cast<char*>(ws) + part_off);
   launch_prep(A, lda, n, o.algo, tab, st);
   int cc = c;
-  uint64_t nch = nchunks;
+  uint64_t ch0 = chunk0, nch = nchunks;
   int plain = o.plain ? 1 : 0;
-  void* args[] = {&tab, &cc, &nch, &parts, &plain};
+  void* args[] = {&tab, &cc, &ch0, &nch, &pw, &plain};
   e = hipLaunchKernel(kern, dim3((unsigned)blocks), dim3(256), args, lds, st);
   if (e != hipSuccess) return hip_fail(e, "sweep launch");
-  launch_finalize_single(parts, (int64_t)nwaves, n, o.algo, o.plain, out, st);
+  *parts = pw;
+  *nparts = (int64_t)nwaves;
+  return PH_OK;
+}
+
+int perm_single(const double2* A, int n, int64_t lda, double2* out, const Opts& o, hipStream_t st, int cus) {
+  hipError_t e;
+  if (n == 0) {
+    launch_finalize_single(nullptr, 0, 0, o.algo, o.plain, out, st);
+    e = hipGetLastError();
+    return e == hipSuccess ? PH_OK : hip_fail(e, "finalize launch");
+  }
+  const int nb = gray_bits(n, o.algo);
+  const int c = pick_chunk_log2(n, o.algo, o.chunk_log2);
+  double4* parts = nullptr;
+  int64_t nparts = 0;
+  int rc = sweep_share(A, n, lda, c, 0, (uint64_t)1 << (nb - c), o, st, cus, &parts, &nparts);
+  if (rc) return rc;
+  launch_finalize_single(parts, nparts, n, o.algo, o.plain, out, st);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return PH_OK;
@@ -220,3 +234,68 @@ int perm_single(const double2* A, int n, int64_t lda, double2* out, const Opts& 
 
 }  // namespace ph
 
+extern "C" int ph_perm_chunk_log2(int32_t n, const ph_opts* opt, int32_t* out) {
+  Opts o;
+  int rc = read_opts(opt, &o);
+  if (rc) return rc;
+  if (n < 1) return fail(PH_EINVAL, "n=%d < 1", n);
+  if (n > PH_NMAX) return fail(PH_ERANGE, "n=%d > %d", n, PH_NMAX);
+  if (!out) return fail(PH_EINVAL, "out is NULL");
+  *out = pick_chunk_log2(n, o.algo, o.chunk_log2);
+  return PH_OK;
+}
+
+extern "C" int ph_perm_partial(const ph_c128* A, int32_t n, int64_t lda, uint64_t k_begin, uint64_t k_end,
+                               double* partial, const ph_opts* opt, void* stream) {
+  Opts o;
+  int rc = read_opts(opt, &o);
+  if (rc) return rc;
+  if (n < 1) return fail(PH_EINVAL, "n=%d < 1", n);
+  if (n > PH_NMAX) return fail(PH_ERANGE, "n=%d > %d", n, PH_NMAX);
+  if (!partial) return fail(PH_EINVAL, "partial is NULL");
+  if (!A) return fail(PH_EINVAL, "A is NULL");
+  if (lda < n) return fail(PH_EINVAL, "lda=%lld < n=%d", (long long)lda, n);
+  const int nb = gray_bits(n, o.algo);
+  const int c = pick_chunk_log2(n, o.algo, o.chunk_log2);
+  const uint64_t total = (uint64_t)1 << nb, mask = ((uint64_t)1 << c) - 1;
+  if (k_begin > k_end || k_end > total)
+    return fail(PH_EINVAL, "term range [%llu, %llu) outside [0, 2^%d)", (unsigned long long)k_begin,
+                (unsigned long long)k_end, nb);
+  if ((k_begin & mask) || (k_end & mask))
+    return fail(PH_EINVAL, "term range [%llu, %llu) not aligned to the chunk length 2^%d",
+                (unsigned long long)k_begin, (unsigned long long)k_end, c);
+  int dev;
+  DevInfo di;
+  if ((rc = device_info(&dev, &di))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  double4* out = reinterpret_cast<double4*>(partial);
+  double4* parts = nullptr;
+  int64_t nparts = 0;
+  if (k_end > k_begin) {
+    rc = sweep_share(reinterpret_cast<const double2*>(A), n, lda, c, k_begin >> c, (k_end - k_begin) >> c, o, st,
+                     di.cus, &parts, &nparts);
+    if (rc) return rc;
+  }
+  launch_reduce_partials(parts, nparts, o.plain ? 1 : 0, out, st);  // zero for an empty range
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? PH_OK : hip_fail(e, "kernel launch");
+}
+
+extern "C" int ph_perm_combine(const double* partials, int64_t count, int32_t n, ph_c128* out, const ph_opts* opt,
+                               void* stream) {
+  Opts o;
+  int rc = read_opts(opt, &o);
+  if (rc) return rc;
+  if (n < 1) return fail(PH_EINVAL, "n=%d < 1", n);
+  if (n > PH_NMAX) return fail(PH_ERANGE, "n=%d > %d", n, PH_NMAX);
+  if (count < 0) return fail(PH_EINVAL, "count=%lld < 0", (long long)count);
+  if (count > 0 && !partials) return fail(PH_EINVAL, "partials is NULL");
+  if (!out) return fail(PH_EINVAL, "out is NULL");
+  int dev;
+  DevInfo di;
+  if ((rc = device_info(&dev, &di))) return rc;
+  launch_finalize_single(reinterpret_cast<const double4*>(partials), count, n, o.algo, o.plain,
+                         reinterpret_cast<double2*>(out), (hipStream_t)stream);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? PH_OK : hip_fail(e, "kernel launch");
+}

@@ -54,6 +54,7 @@ const void* reset_kernel();             // k_reset(counters, count)
 void launch_fill_synthetic(double2* a, int64_t count, hipStream_t st);
 void launch_finalize_single(const double4* partials, int64_t nparts, int n, int algo, int plain, double2* out,
                             hipStream_t st);
+void launch_reduce_partials(const double4* partials, int64_t nparts, int plain, double4* out, hipStream_t st);
 
 }  // namespace ph
 

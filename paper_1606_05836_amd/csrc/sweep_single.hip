@@ -4,12 +4,15 @@
 // the instances build in parallel; each compilation exports one lookup
 // function ph_single_kernel_<lo>_<hi>(n, algo) returning the kernel handle.
 //
-// Work split: the C = 2^nb / 2^c chunks are grouped in "super-chunks" of 64
-// consecutive chunks (one per lane of a wavefront).  Wave w of the grid takes
-// the contiguous super-chunk range [S w / W, S (w+1) / W), S = ceil(C / 64),
-// keeps a double-double (or plain) accumulator per lane across all of it, and
-// writes one partial per wave -- the per-process contiguous ranges and final
-// reduce of the parallel listings, mapped to wavefronts.
+// Work split: the launch covers the C chunks [chunk0, chunk0 + C) of length
+// 2^c (all 2^nb / 2^c of them for a whole permanent, a contiguous share of
+// them for one part of a sharded sum).  They are grouped in "super-chunks" of
+// 64 consecutive chunks (one per lane of a wavefront).  Wave w of the grid
+// takes the contiguous super-chunk range [S w / W, S (w+1) / W),
+// S = ceil(C / 64), keeps a double-double (or plain) accumulator per lane
+// across all of it, and writes one partial per wave -- the per-process
+// contiguous ranges and final reduce of the parallel listings, mapped to
+// wavefronts.
 #include "sweep.hpp"
 #include "ph_internal.hpp"
 
@@ -20,8 +23,8 @@
 namespace ph {
 
 template <int N, int ALGO>
-__global__ __launch_bounds__(256) void k_sweep_single(const double2* __restrict__ tab, int c, uint64_t nchunks,
-                                                      double4* __restrict__ partials, int plain) {
+__global__ __launch_bounds__(256) void k_sweep_single(const double2* __restrict__ tab, int c, uint64_t chunk0,
+                                                      uint64_t nchunks, double4* __restrict__ partials, int plain) {
   const int lane = threadIdx.x & 63;
   const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
@@ -35,7 +38,7 @@ __global__ __launch_bounds__(256) void k_sweep_single(const double2* __restrict_
   dd2 acc = {0.0, 0.0, 0.0, 0.0};
   for (uint64_t s = s0; s < s1; ++s) {
     const uint64_t chunk = (s << 6) + lane;
-    sweep_chunk<N, ALGO>(chunk << c, c, res, lds_tab, acc, plain != 0, chunk < nchunks);
+    sweep_chunk<N, ALGO>((chunk0 + chunk) << c, c, res, lds_tab, acc, plain != 0, chunk < nchunks);
   }
   acc = wave_reduce(acc, plain != 0);
   if (lane == 0) partials[wave] = make_double4(acc.hr, acc.lr, acc.hi, acc.li);

@@ -23,7 +23,7 @@ PH_OK, PH_EINVAL, PH_ERANGE, PH_ENOMEM, PH_EHIP, PH_EUNSUPPORTED = 0, -1, -2, -3
 PH_NMAX, PH_NMAX_GRAD = 52, 32
 PH_FLAG_UNGROUPED = 1
 
-EXPORTS = ("ph_perm", "ph_perm_batched", "ph_plan_create", "ph_plan_execute", "ph_plan_destroy",
+EXPORTS = ("ph_perm", "ph_perm_chunk_log2", "ph_perm_partial", "ph_perm_combine", "ph_perm_batched", "ph_plan_create", "ph_plan_execute", "ph_plan_destroy",
            "ph_perm_grad", "ph_boson_probs", "ph_boson_probs_grad", "ph_fp64_peak", "ph_last_error",
            "ph_version")
 
@@ -54,6 +54,9 @@ def lib() -> ctypes.CDLL:
     op = ctypes.POINTER(PhOpts)
     P = ctypes.POINTER
     L.ph_perm.argtypes = [vp, i32, i64, vp, op, vp]
+    L.ph_perm_chunk_log2.argtypes = [i32, op, P(ctypes.c_int32)]
+    L.ph_perm_partial.argtypes = [vp, i32, i64, ctypes.c_uint64, ctypes.c_uint64, vp, op, vp]
+    L.ph_perm_combine.argtypes = [vp, i64, i32, vp, op, vp]
     L.ph_perm_batched.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int32), i64, vp, op, vp]
     L.ph_plan_create.argtypes = [P(ctypes.c_int32), P(ctypes.c_int64), i64, op, vp, P(ctypes.c_void_p)]
     L.ph_plan_execute.argtypes = [vp, vp, vp, vp]
@@ -123,6 +126,56 @@ def perm(a: torch.Tensor, algo="glynn", accum="dd", chunk_log2: int = 0, waves: 
         out = torch.empty((), dtype=torch.complex128, device=a.device)
     o = opts(algo, accum, chunk_log2, waves)
     check(lib().ph_perm(_ptr(a), n, lda, _ptr(out), ctypes.byref(o), _stream(a)))
+    return out
+
+
+def perm_chunk_log2(n: int, algo="glynn", accum="dd", chunk_log2: int = 0) -> int:
+    """log2 of the chunk length ph_perm / ph_perm_partial use for n; term
+    ranges given to perm_partial are multiples of 2**this."""
+    c = ctypes.c_int32(0)
+    o = opts(algo, accum, chunk_log2)
+    check(lib().ph_perm_chunk_log2(int(n), ctypes.byref(o), ctypes.byref(c)))
+    return int(c.value)
+
+
+def gray_terms(n: int, algo="glynn") -> int:
+    """Number of terms of the Gray-code sum: 2^(n-1) (BB/FG) or 2^n (Ryser)."""
+    return 1 << (n - 1 if opts(algo).algo == PH_GLYNN else n)
+
+
+def perm_partial(a: torch.Tensor, k_begin: int, k_end: int, algo="glynn", accum="dd", chunk_log2: int = 0,
+                 waves: int = 0, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Unscaled signed sum of the terms k in [k_begin, k_end) of Per(a)'s
+    Gray-code sum (ph_perm_partial): a float64 CUDA tensor of 4 values
+    {re_hi, re_lo, im_hi, im_lo}."""
+    _need_c128_cuda("a", a)
+    if a.dim() != 2 or a.shape[0] != a.shape[1]:
+        raise ValueError("a must be n x n")
+    n = a.shape[0]
+    if n > 0 and a.stride(1) != 1:
+        a = a.contiguous()
+    if out is None:
+        out = torch.empty(4, dtype=torch.float64, device=a.device)
+    elif out.dtype != torch.float64 or not out.is_cuda or out.numel() != 4 or not out.is_contiguous():
+        raise ValueError("out must be 4 contiguous float64 values on the GPU")
+    o = opts(algo, accum, chunk_log2, waves)
+    check(lib().ph_perm_partial(_ptr(a), n, a.stride(0) if n > 0 else 1, int(k_begin), int(k_end), _ptr(out),
+                                ctypes.byref(o), _stream(a)))
+    return out
+
+
+def perm_combine(partials: torch.Tensor, n: int, algo="glynn", accum="dd",
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+    """Per from partials (a (count, 4) float64 CUDA tensor, summed in row
+    order) made by perm_partial with the same n, algo and accum."""
+    if partials.dtype != torch.float64 or not partials.is_cuda or partials.shape[-1] != 4:
+        raise TypeError("partials must be a (count, 4) float64 CUDA tensor")
+    partials = partials.reshape(-1, 4).contiguous()
+    if out is None:
+        out = torch.empty((), dtype=torch.complex128, device=partials.device)
+    o = opts(algo, accum)
+    check(lib().ph_perm_combine(_ptr(partials), partials.shape[0], int(n), _ptr(out), ctypes.byref(o),
+                                _stream(partials)))
     return out
 
 

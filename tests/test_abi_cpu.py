@@ -117,3 +117,55 @@ def test_boson_argument_errors_are_reported_before_any_device_work(L):
     assert grad(4, [], [], 0, 1) == P.PH_EINVAL  # the gradient needs n >= 1
     assert grad(4, [0, 1], [0, 1], 1, 2, o=P.PhOpts(P.PH_RYSER, 0, 0, 0, 0)) == P.PH_EINVAL
     assert b"PH_GLYNN" in L.ph_last_error()
+
+
+def test_chunk_length_query(L):
+    from paper_1606_05836_amd import permhip as P
+
+    # default: 2^min(12, nb - 13) terms per chunk, at least 2^4 (2^1 for nb < 4), at most the whole sum
+    assert P.perm_chunk_log2(40) == 12
+    assert P.perm_chunk_log2(20) == 6
+    assert P.perm_chunk_log2(20, "ryser") == 7
+    assert P.perm_chunk_log2(3) == 1
+    assert P.perm_chunk_log2(1) == 0
+    assert P.perm_chunk_log2(1, "ryser") == 1
+    assert P.perm_chunk_log2(30, chunk_log2=9) == 9
+    assert P.perm_chunk_log2(8, chunk_log2=40) == 7  # clamped to the 2^7 terms
+    assert P.gray_terms(40) == 1 << 39 and P.gray_terms(40, "ryser") == 1 << 40
+    c = ctypes.c_int32(0)
+    assert L.ph_perm_chunk_log2(0, None, ctypes.byref(c)) == P.PH_EINVAL
+    assert L.ph_perm_chunk_log2(P.PH_NMAX + 1, None, ctypes.byref(c)) == P.PH_ERANGE
+    assert L.ph_perm_chunk_log2(10, None, None) == P.PH_EINVAL
+
+
+def test_partial_and_combine_argument_errors(L):
+    from paper_1606_05836_amd import permhip as P
+
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+    def part(n, kb, ke, lda=None, a=fake, out=fake, o=None):
+        return L.ph_perm_partial(a, n, n if lda is None else lda, kb, ke, out, ctypes.byref(o) if o else None, None)
+
+    L16 = 1 << 12  # n = 40: chunks of 2^12 terms
+    assert part(0, 0, 0) == P.PH_EINVAL
+    assert part(P.PH_NMAX + 1, 0, 0) == P.PH_ERANGE
+    assert part(40, 0, L16, a=None) == P.PH_EINVAL
+    assert part(40, 0, L16, out=None) == P.PH_EINVAL
+    assert part(40, 0, L16, lda=39) == P.PH_EINVAL
+    assert part(40, L16, 0) == P.PH_EINVAL  # begin > end
+    assert part(40, 0, (1 << 39) + L16) == P.PH_EINVAL  # past the 2^39 terms
+    assert b"outside" in L.ph_last_error()
+    assert part(40, 1, L16) == P.PH_EINVAL  # not a chunk boundary
+    assert b"aligned" in L.ph_last_error()
+    assert part(40, 0, L16 + 8) == P.PH_EINVAL
+    assert part(40, 0, 1 << 12, o=P.PhOpts(0, 0, 13, 0, 0)) == P.PH_EINVAL  # 2^12 is not a 2^13 multiple
+    assert part(40, 0, L16, o=P.PhOpts(3, 0, 0, 0, 0)) == P.PH_EINVAL
+
+    def comb(parts, count, n, out=fake):
+        return L.ph_perm_combine(parts, count, n, out, None, None)
+
+    assert comb(fake, 1, 0) == P.PH_EINVAL
+    assert comb(fake, 1, P.PH_NMAX + 1) == P.PH_ERANGE
+    assert comb(fake, -1, 10) == P.PH_EINVAL
+    assert comb(None, 2, 10) == P.PH_EINVAL
+    assert comb(fake, 1, 10, out=None) == P.PH_EINVAL

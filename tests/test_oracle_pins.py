@@ -191,6 +191,61 @@ def test_gray_range_split_is_exact():
     assert O.glynn_raw_parallel(g, 0, total, workers=2) == full
 
 
+def _term_by_convention(a, k, algo):
+    """The summand of Gray index k written straight from the convention the
+    library documents for its partial sums (word w = k ^ (k >> 1); BB/FG:
+    delta_0 = +1, delta_{b+1} = -1 iff bit b of w; Ryser: column b in S iff
+    bit b of w), in exact integer arithmetic on an integer matrix."""
+    n = a.shape[0]
+    w = k ^ (k >> 1)
+    if algo == "glynn":
+        coef = [1] + [-1 if (w >> b) & 1 else 1 for b in range(n - 1)]
+        sign = int(np.prod(coef))
+    else:
+        coef = [1 if (w >> b) & 1 else 0 for b in range(n)]
+        sign = (-1) ** sum(coef)
+    prod = 1
+    for i in range(n):
+        prod *= sum(coef[j] * complex(a[i, j]) for j in range(n))
+    return complex(sign * prod)
+
+
+@pytest.mark.parametrize("algo", ["glynn", "ryser"])
+def test_single_index_ranges_follow_the_documented_word_convention(algo):
+    # small integer entries: every product is exact in binary64
+    a = gauss_int_matrix(5, 77, -2, 2)
+    g, d = O.to_gaussian_integers(a)
+    assert d == 1
+    raw = O.glynn_gray_raw if algo == "glynn" else O.ryser_gray_raw
+    for k in range(1 << (4 if algo == "glynn" else 5)):
+        got = raw(g, k, k + 1)
+        assert complex(got[0], got[1]) == _term_by_convention(a, k, algo), k
+
+
+@pytest.mark.parametrize("n", range(1, 7))
+def test_ryser_gray_range_is_eq_s1(n):
+    for seed in (0, 1):
+        a = gauss_int_matrix(n, 900 + seed)
+        g, _ = O.to_gaussian_integers(a)
+        re, im = O.ryser_gray_raw(g)
+        sg = (-1) ** n
+        assert (sg * re, sg * im) == O.perm_brute_int(g)
+        assert (sg * re, sg * im) == O.ryser_subsets_int(g)
+
+
+def test_ryser_gray_range_split_and_closed_form():
+    g, _ = O.to_gaussian_integers(gauss_int_matrix(8, 12))
+    full = O.ryser_gray_raw(g)
+    for pieces in (1, 3, 16, 256):
+        parts = [O.ryser_gray_raw(g, a, b) for a, b in O.split_range(1 << 8, pieces)]
+        assert (sum(p[0] for p in parts), sum(p[1] for p in parts)) == full
+    assert O.ryser_gray_raw(g, 0, 1) == (0, 0)  # the empty set
+    # all ones: sum_S (-1)^|S| |S|^n = (-1)^n n!
+    for n in range(1, 8):
+        ones = [[(1, 0)] * n for _ in range(n)]
+        assert O.ryser_gray_raw(ones) == ((-1) ** n * math.factorial(n), 0)
+
+
 # ------------------------------------------------------ values the paper prints
 
 def _printed_match(value: float, printed: str) -> bool:
