@@ -159,6 +159,22 @@ def extras(ph, dev, stream):
         "workload": "dL/dA of L = |perm(A)|^2, 1024 x (20 x 20) rows of Haar(400, 41) (seed 42)",
         "fwd_ms": fwd, "grad_ms": bwd, "ratio": bwd / fwd,
     }
+    # one device's share of the largest orders (two lanes per term), with
+    # the full-sum time it implies on 1 and on 8 devices (a projection)
+    res["large_share"] = {}
+    for n in (48, 50):
+        an = torch.from_numpy(inputs.config3_matrix(n)).to(dev)
+        total = 1 << (n - 1)
+        kb, m = 3 * (total // 8), 1 << 37
+        ph.perm_partial(an, kb, kb + (1 << 24))
+        ms = _median(_event_ms(lambda: ph.perm_partial(an, kb, kb + m), 1, stream))
+        tps = m / (ms / 1e3)
+        _log(f"share n={n}: {ms:.1f} ms for 2^37 terms, {tps:.3e} terms/s")
+        res["large_share"][str(n)] = {
+            "workload": f"terms [3 * 2^{n - 1} / 8, + 2^37) of Per(A), A = {n} x {n} block of Haar(1600, 31)",
+            "ms": ms, "terms_per_s": tps, "frac_fp64_peak": tps * flops_per_term(n) / 1e12 / PEAK_FP64_VECTOR_TFLOPS,
+            "projected_full_s_1gpu": total / tps, "projected_full_s_8gpu": total / tps / 8,
+        }
     # boson sampling: Eq. (1) probabilities and their gradient
     u, ins, pats = inputs.config5_workload()
     ud = torch.from_numpy(u).to(dev)

@@ -94,20 +94,22 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     with open(os.path.join(OUT, "resources.txt"), "w") as f:
         for k in sorted(report):
             f.write(k + " " + " ".join(f"{a}={b}" for a, b in sorted(report[k].items())) + "\n")
-    def _n_of(kernel):
+    def _uses_dpp(kernel):
         m = re.search(r"sweep_\w*?ILi(\d+)E(Li(\d+)E)?", kernel)
         if not m:
-            return 0
-        # batched kernels are templated on the bucket bounds: take the lower
-        # one, DPP is used there up to BATCHED_DPP_NMAX
+            return False
+        # batched kernels are templated on the bucket bounds: DPP is used
+        # there when the bucket starts at or below BATCHED_DPP_NMAX
         if "batched" in kernel:
-            lo, hi = int(m.group(1)), int(m.group(3) or m.group(1))
-            return hi if lo <= BATCHED_DPP_NMAX else DPP_NMAX + 1
-        return int(m.group(1))
+            return int(m.group(1)) <= BATCHED_DPP_NMAX
+        # one-matrix sweeps: one lane per term up to DPP_NMAX, two lanes per
+        # term from PAIR_NMIN on (csrc/sweep_pair.hpp); both keep resident
+        # columns
+        return True
 
-    # kernels up to DPP_NMAX (sweep.hpp) read resident columns with DPP: no
-    # spill code of any kind (AGPR copies included) is allowed there
-    bad = [k for k, v in report.items() if "sweep" in k and _n_of(k) <= DPP_NMAX and (
+    # kernels that read resident columns with DPP: no spill code of any kind
+    # (AGPR copies included) is allowed there
+    bad = [k for k, v in report.items() if "sweep" in k and _uses_dpp(k) and (
         v.get("VGPRs Spill", "0") != "0" or v.get("SGPRs Spill", "0") != "0" or v.get("AGPRs", "0") != "0")]
     if bad:
         raise RuntimeError("sweep kernels spill registers: " + ", ".join(bad[:8]))

@@ -184,7 +184,7 @@ static int sweep_share(const double2* A, int n, int64_t lda, int c, uint64_t chu
   const uint64_t nsuper = (nchunks + 63) / 64;
   const void* kern = single_kernel(n, o.algo);
   if (!kern) return fail(PH_ERANGE, "no kernel for n=%d", n);
-  const size_t lds = (size_t)n * n * sizeof(double2);
+  const size_t lds = single_lds_bytes(n);
   int per_cu = 0;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds);
   if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");

@@ -11,6 +11,11 @@ constexpr int NMAX_GRAD = 32;  // largest n of the backward sweep
 // Complex entries of the per-matrix table (n columns of n entries; a table
 // with ncols < n columns uses the first ncols * n of them).
 inline size_t table_elems(int n) { return (size_t)n * n; }
+// LDS of the one-matrix sweep: the table, with its column stride padded to an
+// even row count where two lanes share a term (n >= 45)
+inline size_t single_lds_bytes(int n) {
+  return (size_t)n * (n >= 45 ? 2 * ((n + 1) / 2) : n) * 16;
+}
 
 // Per-matrix descriptor used by the batched kernels (device memory).
 struct MatDesc {

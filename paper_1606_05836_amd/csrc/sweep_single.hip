@@ -7,13 +7,15 @@
 // Work split: the launch covers the C chunks [chunk0, chunk0 + C) of length
 // 2^c (all 2^nb / 2^c of them for a whole permanent, a contiguous share of
 // them for one part of a sharded sum).  They are grouped in "super-chunks" of
-// 64 consecutive chunks (one per lane of a wavefront).  Wave w of the grid
+// 64 consecutive chunks (one per lane of a wavefront; 32 for n >= PAIR_NMIN,
+// where two lanes share a chunk, see sweep_pair.hpp).  Wave w of the grid
 // takes the contiguous super-chunk range [S w / W, S (w+1) / W),
 // S = ceil(C / 64), keeps a double-double (or plain) accumulator per lane
 // across all of it, and writes one partial per wave -- the per-process
 // contiguous ranges and final reduce of the parallel listings, mapped to
 // wavefronts.
 #include "sweep.hpp"
+#include "sweep_pair.hpp"
 #include "ph_internal.hpp"
 
 #ifndef PH_NLO
@@ -28,17 +30,34 @@ __global__ __launch_bounds__(256) void k_sweep_single(const double2* __restrict_
   const int lane = threadIdx.x & 63;
   const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
-  const uint64_t nsuper = (nchunks + 63) >> 6;
-  const uint64_t s0 = nsuper * wave / nwaves;
-  const uint64_t s1 = nsuper * (wave + 1) / nwaves;
   extern __shared__ double2 lds_tab[];
-  stage_table<N>(lds_tab, tab);
-  Resident<N, ALGO> res;
-  res.load(lds_tab);
   dd2 acc = {0.0, 0.0, 0.0, 0.0};
-  for (uint64_t s = s0; s < s1; ++s) {
-    const uint64_t chunk = (s << 6) + lane;
-    sweep_chunk<N, ALGO>((chunk0 + chunk) << c, c, res, lds_tab, acc, plain != 0, chunk < nchunks);
+  if constexpr (N >= PAIR_NMIN) {
+    // two lanes per chunk: super-chunks of 32 chunks
+    const bool upper = lane >= 32;
+    const uint64_t nsuper = (nchunks + 31) >> 5;
+    const uint64_t s0 = nsuper * wave / nwaves;
+    const uint64_t s1 = nsuper * (wave + 1) / nwaves;
+    stage_table_pair<N, ALGO>(lds_tab, tab);
+    const double2* Tl = lds_tab + (upper ? PairShape<N, ALGO>::R : 0);
+    ResidentPair<N, ALGO> res;
+    res.load(Tl);
+    for (uint64_t s = s0; s < s1; ++s) {
+      const uint64_t chunk = (s << 5) + (lane & 31);
+      sweep_chunk_pair<N, ALGO>((chunk0 + chunk) << c, c, res, Tl, upper, acc, plain != 0,
+                                chunk < nchunks && !upper);
+    }
+  } else {
+    const uint64_t nsuper = (nchunks + 63) >> 6;
+    const uint64_t s0 = nsuper * wave / nwaves;
+    const uint64_t s1 = nsuper * (wave + 1) / nwaves;
+    stage_table<N>(lds_tab, tab);
+    Resident<N, ALGO> res;
+    res.load(lds_tab);
+    for (uint64_t s = s0; s < s1; ++s) {
+      const uint64_t chunk = (s << 6) + lane;
+      sweep_chunk<N, ALGO>((chunk0 + chunk) << c, c, res, lds_tab, acc, plain != 0, chunk < nchunks);
+    }
   }
   acc = wave_reduce(acc, plain != 0);
   if (lane == 0) partials[wave] = make_double4(acc.hr, acc.lr, acc.hi, acc.li);

@@ -183,3 +183,58 @@ def test_segmented_run_resumes_to_the_same_bits(ph, tmp_path):
 
     shards = [segmented_perm(a, segment_log2=20, shard=(g, 3)) for g in range(3)]
     assert combine_shards(shards) == ref.total()
+
+
+@pytest.mark.parametrize("algo,n,c", [("glynn", 45, 6), ("glynn", 48, 6), ("glynn", 52, 6), ("ryser", 45, 6),
+                                      ("ryser", 47, 6), ("ryser", 52, 6), ("glynn", 48, 0)])
+def test_large_n_haar_ranges_against_oracle(ph, algo, n, c):
+    # orders 45..52 sweep each term over two lanes (rows split in halves, odd n
+    # padded); short ranges high in the index space against the exact sums
+    a = I.config3_matrix(n)
+    g, d = O.to_gaussian_integers(a)
+    scale = Fraction(1, d ** n)
+    cc = ph.perm_chunk_log2(n, algo, chunk_log2=c)
+    L = 1 << cc
+    total = ph.gray_terms(n, algo)
+    k0 = (total // 3) // L * L + 5 * L
+    nch = 3 if cc <= 6 else 1
+    at = cuda(a)
+    for kb, ke in ((k0, k0 + nch * L), (k0 + L, k0 + L), (total - L, total)):
+        p = ph.perm_partial(at, kb, ke, algo=algo, chunk_log2=c).cpu().tolist()
+        re, im = raw_exact(g, algo, kb, ke)
+        e = complex(float(re * scale), float(im * scale))
+        v = complex(p[0] + p[1], p[2] + p[3])
+        if kb == ke:
+            assert v == 0
+        else:
+            assert abs(v - e) <= 1e-12 * abs(e), (kb, ke, v, e)
+
+
+@pytest.mark.parametrize("n", [45, 47])
+def test_odd_large_n_shares_exact_on_diag_one_plus_i(ph, n):
+    # odd orders pad the upper half with a row whose sum stays 1
+    a = cuda(I.diag_matrix(n, 1 + 1j))
+    m = 1 << 30
+    kb = (1 << (n - 3)) + (7 << 30)
+    p = ph.perm_partial(a, kb, kb + m).cpu().tolist()
+    want = m * (1 + 1j) * 2 ** ((n - 1) // 2) * 1j ** ((n - 1) // 2)
+    assert complex(p[0] + p[1], p[2] + p[3]) == want
+
+
+@pytest.mark.parametrize("n", [45, 46, 51])
+def test_ryser_diag_full_set_term(ph, n):
+    # Eq. (S1) on diag(d): only S = all columns contributes, (-1)^n prod d,
+    # at the index whose Gray word has every bit set
+    a = cuda(I.diag_matrix(n, 1 + 1j))
+    k_all = 0
+    for i in range(n):
+        if (n - i) % 2:
+            k_all |= 1 << i
+    assert k_all ^ (k_all >> 1) == (1 << n) - 1
+    L = 1 << ph.perm_chunk_log2(n, "ryser")
+    kb = k_all // L * L
+    p = ph.perm_partial(a, kb, kb + L, algo="ryser").cpu().tolist()
+    want = (-1) ** n * (1 + 1j) ** (n % 2) * 2 ** (n // 2) * 1j ** (n // 2)
+    assert complex(p[0] + p[1], p[2] + p[3]) == want
+    p = ph.perm_partial(a, kb - 4 * L, kb, algo="ryser").cpu().tolist()
+    assert p == [0.0, 0.0, 0.0, 0.0]
