@@ -4,10 +4,9 @@
 // Lane l and lane l + 32 of a wavefront walk the same chunk.  The lower lane
 // owns rows 0..R-1 and the upper lane rows R..2R-1, R = ceil(n/2); for odd n
 // the last row of the upper half is padding whose row sum stays 1.  Each lane
-// forms the product of its R row sums; one v_permlane32_swap per dword then
-// leaves the lower half's product in one register and the upper half's in
-// another on every lane, and their complex product is the term of Eq. (S1) or
-// (S2).  Only the lower lane accumulates it.
+// forms the product of its R row sums; one v_permlane32_swap per dword brings
+// the upper lane's product to the lower lane, whose complex product of the two
+// is the term of Eq. (S1) or (S2).  Only the lower lane accumulates it.
 //
 // Every 16-lane DPP row lies in one half, so the low update columns stay
 // resident in VGPRs (row_newbcast), as in the one-lane sweep: each lane's row
@@ -92,18 +91,23 @@ __device__ __forceinline__ void seed_pair(double2 (&r)[R], uint64_t k0, const do
   }
 }
 
-// Value of lane (l mod 32) and of lane (l mod 32) + 32, on every lane l.
-__device__ __forceinline__ void both_halves(double x, double& lower, double& upper) {
-  const unsigned lo = (unsigned)__double2loint(x), hi = (unsigned)__double2hiint(x);
-  const auto pl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-  const auto ph = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-  lower = __hiloint2double((int)ph[0], (int)pl[0]);
-  upper = __hiloint2double((int)ph[1], (int)pl[1]);
+// On a lower lane l: x keeps its value and `from` receives x of lane l + 32.
+// (v_permlane32_swap exchanges the upper half of its first operand with the
+// lower half of its second; `from` enters with a dead value, the previous
+// term's, so no copy is needed.  On upper lanes both results are unused.)
+__device__ __forceinline__ void from_upper(double& x, double& from) {
+  const unsigned xl = (unsigned)__double2loint(x), xh = (unsigned)__double2hiint(x);
+  const unsigned fl = (unsigned)__double2loint(from), fh = (unsigned)__double2hiint(from);
+  const auto pl = __builtin_amdgcn_permlane32_swap(xl, fl, false, false);
+  const auto ph = __builtin_amdgcn_permlane32_swap(xh, fh, false, false);
+  x = __hiloint2double((int)ph[0], (int)pl[0]);
+  from = __hiloint2double((int)ph[1], (int)pl[1]);
 }
 
-// sb += (+-) (product of the lower half's rows) * (product of the upper half's).
+// On lower lanes: sb += (+-) (product of the lower half's rows) * (product of
+// the upper half's).  `up` carries the received product from term to term.
 template <int R>
-__device__ __forceinline__ void term_pair(const double2 (&r)[R], double2& sb, bool neg) {
+__device__ __forceinline__ void term_pair(const double2 (&r)[R], double2& sb, double2& up, bool neg) {
   constexpr int K = R < 4 ? R : 4;
   double2 ch[K];
 #pragma unroll
@@ -114,9 +118,9 @@ __device__ __forceinline__ void term_pair(const double2 (&r)[R], double2& sb, bo
   if constexpr (K == 2) x = cmul(ch[0], ch[1]);
   if constexpr (K == 3) x = cmul(cmul(ch[0], ch[1]), ch[2]);
   if constexpr (K == 4) x = cmul(cmul(ch[0], ch[1]), cmul(ch[2], ch[3]));
-  double2 lo, up;
-  both_halves(x.x, lo.x, up.x);
-  both_halves(x.y, lo.y, up.y);
+  double2 lo = x;
+  from_upper(lo.x, up.x);
+  from_upper(lo.y, up.y);
   if (neg) {
     lo.x = -lo.x;
     lo.y = -lo.y;
@@ -137,10 +141,10 @@ __device__ __forceinline__ void sweep_chunk_pair(uint64_t k0, int c, const Resid
   static_assert(LOGU == 4, "the pair sweep is for large orders");
   double2 r[R];
   seed_pair<N, ALGO>(r, k0, Tl, upper);
-  double2 sb = make_double2(0.0, 0.0);
+  double2 sb = make_double2(0.0, 0.0), up = make_double2(0.0, 0.0);
   const double one = 1.0, mone = -1.0;
   const uint32_t nblk = 1u << (c - LOGU);
-  term_pair<R>(r, sb, (k0 & 1) != 0);  // offset 0
+  term_pair<R>(r, sb, up, (k0 & 1) != 0);  // offset 0
   for (uint32_t m = 0; m < nblk; ++m) {
     const uint32_t tb = m << LOGU;
     static_for<1, U>([&](auto sc) {
@@ -157,14 +161,14 @@ __device__ __forceinline__ void sweep_chunk_pair(uint64_t k0, int c, const Resid
         add_resident<R, P::NP>(r, res.col[b], sg);
       else
         fma_lds<R>(r, sg, Tl + (b + P::OFF) * P::RS);
-      term_pair<R>(r, sb, (s & 1) != 0);
+      term_pair<R>(r, sb, up, (s & 1) != 0);
       __builtin_amdgcn_sched_barrier(0);
     });
     if (m + 1 < nblk) {
       const int b = LOGU + __builtin_ctz(m + 1);
       const uint64_t k = k0 + tb + U;
       fma_lds<R>(r, ((k >> (b + 1)) & 1) ? -1.0 : 1.0, Tl + (b + P::OFF) * P::RS);
-      term_pair<R>(r, sb, false);
+      term_pair<R>(r, sb, up, false);
     }
     flush(acc, sb, plain, active);
   }
