@@ -29,3 +29,10 @@ from .boson import (  # noqa: F401
     perm_multiplicity,
     prob_multiplicity,
 )
+from .sampler import (  # noqa: F401
+    columns_of_inputs,
+    step_weights,
+    choose,
+    sample_exact,
+    sampler_distribution,
+)

@@ -37,6 +37,9 @@ from .pool import perm_exact_parallel
 def gather_u_st(u: np.ndarray, in_modes, out_modes) -> np.ndarray:
     """U_{S,T}: rows = output modes (with repeats), columns = input modes
     (with repeats), both in the given order."""
+    if isinstance(u, list):
+        # exact entries (e.g. (re, im) Fraction pairs) stay Python objects
+        return [[u[int(i)][int(j)] for j in in_modes] for i in out_modes]
     u = np.asarray(u)
     return np.ascontiguousarray(u[np.asarray(out_modes)][:, np.asarray(in_modes)])
 
