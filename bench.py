@@ -182,9 +182,15 @@ def extras(ph, dev, stream):
     pf = _median(_event_ms(lambda: ph.boson_probs(ud, ins, pats), 3, stream))
     pg = _median(_event_ms(lambda: ph.boson_probs_grad(ud, ins, pats), 2, stream))
     _log(f"boson: probs {pf:.1f} ms, gradient {pg:.1f} ms")
+    # chain-rule samples of the same 30-photon, 900-mode experiment
+    perms, unis = ph.sample_inputs(64, len(ins), 53)
+    ph.boson_sample(ud, ins, perms=perms[:2], uniforms=unis[:2])
+    ps = _median(_event_ms(lambda: ph.boson_sample(ud, ins, perms=perms, uniforms=unis), 1, stream))
+    _log(f"boson: 64 samples in {ps:.1f} ms")
     res["boson"] = {
         "workload": "U = Haar(900, 51), inputs in modes 0..29, 256 collision patterns (seed 52)",
         "probs_ms": pf, "probs_per_s": len(pats) / (pf / 1e3), "grad_ms": pg, "grad_fwd_ratio": pg / pf,
+        "samples_64_ms": ps, "samples_per_s": 64 / (ps / 1e3),
     }
     return res
 

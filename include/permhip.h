@@ -54,6 +54,7 @@ typedef struct {
 enum { PH_GLYNN = 0, PH_RYSER = 1 };
 enum { PH_ACC_DD = 0, PH_ACC_PLAIN = 1 };
 #define PH_FLAG_UNGROUPED 1u
+#define PH_FLAG_UNSORTED 2u
 
 /* Options; pass NULL for the defaults (Glynn, double-double, tuned sizes).
  *   algo        PH_GLYNN or PH_RYSER
@@ -63,7 +64,9 @@ enum { PH_ACC_DD = 0, PH_ACC_PLAIN = 1 };
  *               range the kernel supports for n are clamped.
  *   waves       wavefronts per SIMD to launch (1..8); 0 = library choice
  *   flags       0, or PH_FLAG_UNGROUPED (ph_boson_probs only: one full sweep
- *               per pattern instead of the multiplicity-grouped sweeps) */
+ *               per pattern instead of the multiplicity-grouped sweeps), or
+ *               PH_FLAG_UNSORTED (ph_boson_sample only: out_modes in the
+ *               order the photons were placed, r_1..r_n) */
 typedef struct {
   int32_t algo;
   int32_t accum;
@@ -192,6 +195,28 @@ int ph_boson_probs(const ph_c128* U, int32_t m, int64_t ldu, const int32_t* in_m
 int ph_boson_probs_grad(const ph_c128* U, int32_t m, int64_t ldu, const int32_t* in_modes, int32_t n,
                         const int32_t* patterns, int64_t n_patterns, const double* weights, double* probs,
                         ph_c128* dU, int64_t lddu, const ph_opts* opt, void* stream);
+
+/* Boson-sampling outputs, drawn by the chain rule over the output photons.
+ * The paper's simulation serves sampling from main-text Eq. (1) but gives no
+ * sampler; this is Clifford and Clifford's exact algorithm (2018).  With
+ * A = U[:, in_modes] (rows = output modes) and the columns of A taken in the
+ * order perms[s] (a permutation of 0..n-1 per sample), photon k = 1..n of
+ * sample s goes to output mode r_k with probability proportional to
+ *   w_k(i) = |Per(A[(r_1, ..., r_{k-1}, i), columns 1..k])|^2,
+ * computed from the minors along the last row (one gradient sweep of k x k
+ * matrices per step, for all samples at once); r_k is the first mode whose
+ * running sum of weights (in mode order) exceeds uniforms[s][k-1] times their
+ * total.  out_modes[s] (device, n int32) receives r sorted ascending (in
+ * placement order under PH_FLAG_UNSORTED): for a unitary U and uniformly
+ * random perms and uniforms, a draw from Eq. (1).
+ *   U (device, m x m, row stride ldu), in_modes (host, n distinct modes),
+ *   1 <= n <= PH_NMAX_GRAD; perms (host, nsamples x n int32) and uniforms
+ *   (host, nsamples x n doubles in [0, 1)) are checked and copied before the
+ *   call returns.  opt->accum selects the sweeps' accumulation; opt->algo must
+ *   be PH_GLYNN.  Weights that are all zero or NaN put the photon in mode 0. */
+int ph_boson_sample(const ph_c128* U, int32_t m, int64_t ldu, const int32_t* in_modes, int32_t n, int64_t nsamples,
+                    const int32_t* perms, const double* uniforms, int32_t* out_modes, const ph_opts* opt,
+                    void* stream);
 
 /* Achieved FP64 FMA rate of this device (microbenchmark, the FMA-only
  * reference program of the paper's Supplementary efficiency section): every

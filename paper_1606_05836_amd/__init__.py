@@ -8,6 +8,8 @@ from .permhip import (  # noqa: F401
     Plan,
     boson_probs,
     boson_probs_grad,
+    boson_sample,
+    sample_inputs,
     fp64_peak,
     lib,
     perm,

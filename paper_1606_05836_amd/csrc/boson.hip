@@ -130,10 +130,6 @@ static std::map<std::pair<int, hipStream_t>, Staging> g_stage;
 
 // Copy the host pieces into device memory at base + off[q] (piece q), one
 // transfer of off[npc] bytes on `st` through the pinned staging buffer.
-struct Piece {
-  const void* src;
-  size_t bytes;
-};
 static int upload_at(hipStream_t st, void* base, const size_t* off, const Piece* pc, int npc) {
   const size_t bytes = off[npc];
   if (bytes == 0) return PH_OK;
@@ -172,7 +168,7 @@ static int upload_at(hipStream_t st, void* base, const size_t* off, const Piece*
 }
 
 // Pieces packed back to back at 256-byte boundaries.
-static int upload(hipStream_t st, void* dst, const Piece* pc, int npc) {
+int upload(hipStream_t st, void* dst, const Piece* pc, int npc) {
   std::vector<size_t> off(npc + 1, 0);
   for (int q = 0; q < npc; ++q) off[q + 1] = off[q] + up256(pc[q].bytes);
   return upload_at(st, dst, off.data(), pc, npc);

@@ -123,8 +123,9 @@ int read_opts(const ph_opts* o, Opts* r) {
     if (o->accum != PH_ACC_DD && o->accum != PH_ACC_PLAIN) return fail(PH_EINVAL, "opts.accum=%d", o->accum);
     if (o->chunk_log2 < 0 || o->chunk_log2 > 62) return fail(PH_EINVAL, "opts.chunk_log2=%d", o->chunk_log2);
     if (o->waves < 0 || o->waves > 8) return fail(PH_EINVAL, "opts.waves=%d", o->waves);
-    if ((o->flags & ~PH_FLAG_UNGROUPED) != 0) return fail(PH_EINVAL, "opts.flags=%u", o->flags);
+    if ((o->flags & ~(PH_FLAG_UNGROUPED | PH_FLAG_UNSORTED)) != 0) return fail(PH_EINVAL, "opts.flags=%u", o->flags);
     d.ungrouped = (o->flags & PH_FLAG_UNGROUPED) != 0;
+    d.unsorted = (o->flags & PH_FLAG_UNSORTED) != 0;
     d.algo = o->algo;
     d.plain = o->accum == PH_ACC_PLAIN;
     d.chunk_log2 = o->chunk_log2;

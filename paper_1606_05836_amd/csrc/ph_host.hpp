@@ -16,6 +16,7 @@ struct Opts {
   int chunk_log2 = 0;  // 0 = library choice
   int waves = 0;       // waves per SIMD, 0 = occupancy limit
   bool ungrouped = false;  // boson probabilities: no multiplicity grouping
+  bool unsorted = false;   // boson samples: placement order
 };
 
 int fail(int code, const char* fmt, ...);
@@ -28,6 +29,20 @@ int gray_bits(int n, int algo);
 int min_chunk_log2(int nb);
 int pick_chunk_log2(int n, int algo, int requested);
 int perm_single(const double2* A, int n, int64_t lda, double2* out, const Opts& o, hipStream_t st, int cus);
+
+// Host arrays copied to device memory in one transfer through a per-stream
+// pinned staging buffer (boson.hip): piece q lands at dst + the sum of the
+// previous pieces' sizes, each rounded up to 256 bytes.  Returns before the
+// copy completes; the host arrays may be reused at once.
+struct Piece {
+  const void* src;
+  size_t bytes;
+};
+int upload(hipStream_t st, void* dst, const Piece* pc, int npc);
+
+// Gradient sweep of `batch` contiguous n x n matrices (grad.hip).
+int perm_grad_launch(const double2* A, int n, int64_t batch, const double2* gout, double2* pout, double2* grad,
+                     const Opts& o, hipStream_t st, int cus);
 
 // Batched sweep over caller-built tables (plan.cpp).
 struct PlanImpl;

@@ -22,9 +22,10 @@ PH_ACC_DD, PH_ACC_PLAIN = 0, 1
 PH_OK, PH_EINVAL, PH_ERANGE, PH_ENOMEM, PH_EHIP, PH_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PH_NMAX, PH_NMAX_GRAD = 52, 32
 PH_FLAG_UNGROUPED = 1
+PH_FLAG_UNSORTED = 2
 
 EXPORTS = ("ph_perm", "ph_perm_chunk_log2", "ph_perm_partial", "ph_perm_combine", "ph_perm_batched", "ph_plan_create", "ph_plan_execute", "ph_plan_destroy",
-           "ph_perm_grad", "ph_boson_probs", "ph_boson_probs_grad", "ph_fp64_peak", "ph_last_error",
+           "ph_perm_grad", "ph_boson_probs", "ph_boson_probs_grad", "ph_boson_sample", "ph_fp64_peak", "ph_last_error",
            "ph_version")
 
 
@@ -65,6 +66,8 @@ def lib() -> ctypes.CDLL:
     L.ph_boson_probs.argtypes = [vp, i32, i64, P(ctypes.c_int32), i32, P(ctypes.c_int32), i64, dp, op, vp]
     L.ph_boson_probs_grad.argtypes = [vp, i32, i64, P(ctypes.c_int32), i32, P(ctypes.c_int32), i64, dp, dp, vp,
                                       i64, op, vp]
+    L.ph_boson_sample.argtypes = [vp, i32, i64, P(ctypes.c_int32), i32, i64, P(ctypes.c_int32), P(ctypes.c_double),
+                                  vp, op, vp]
     L.ph_fp64_peak.argtypes = [i64, P(ctypes.c_double), P(ctypes.c_double), vp]
     L.ph_last_error.restype = ctypes.c_char_p
     L.ph_last_error.argtypes = []
@@ -338,6 +341,48 @@ def boson_probs_grad(u: torch.Tensor, in_modes, patterns, weights: torch.Tensor 
     check(lib().ph_boson_probs_grad(_ptr(u), m, u.stride(0), _i32p(ins), n, _i32p(pats), npat, _ptr(w),
                                     _ptr(probs), _ptr(du), du.stride(0), ctypes.byref(o), _stream(u)))
     return probs, du
+
+
+def sample_inputs(nsamples: int, n: int, seed=None):
+    """Random inputs of the sampler: a uniformly random column order and n
+    uniforms in [0, 1) per sample (numpy's default generator)."""
+    rng = np.random.default_rng(seed)
+    perms = rng.permuted(np.tile(np.arange(n, dtype=np.int32), (nsamples, 1)), axis=1)
+    return np.ascontiguousarray(perms, dtype=np.int32), rng.random((nsamples, n))
+
+
+def boson_sample(u: torch.Tensor, in_modes, nsamples: int | None = None, perms=None, uniforms=None, seed=None,
+                 accum="dd", unsorted: bool = False, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Boson-sampling outputs (ph_boson_sample): an (nsamples, n) int32 CUDA
+    tensor, each row the sorted output modes of one sample (the placement
+    order r_1..r_n with unsorted=True, PH_FLAG_UNSORTED).  perms
+    (nsamples x n, a permutation of 0..n-1 per row) and uniforms (nsamples x n
+    in [0, 1)) are host arrays; when both are None they are drawn with
+    sample_inputs(nsamples, n, seed)."""
+    u = _need_square_u(u)
+    m = u.shape[0]
+    ins, _ = _modes(in_modes, np.zeros((0, len(in_modes)), np.int32), m)
+    n = ins.shape[0]
+    if perms is None and uniforms is None:
+        if nsamples is None:
+            raise ValueError("give nsamples, or perms and uniforms")
+        perms, uniforms = sample_inputs(int(nsamples), n, seed)
+    if perms is None or uniforms is None:
+        raise ValueError("give both perms and uniforms, or neither")
+    perms = np.ascontiguousarray(np.asarray(perms, dtype=np.int64).reshape(-1, n).astype(np.int32))
+    uniforms = np.ascontiguousarray(np.asarray(uniforms, dtype=np.float64).reshape(-1, n))
+    ns = perms.shape[0]
+    if uniforms.shape[0] != ns or (nsamples is not None and int(nsamples) != ns):
+        raise ValueError("perms and uniforms need one row per sample")
+    if out is None:
+        out = torch.empty((ns, n), dtype=torch.int32, device=u.device)
+    elif out.dtype != torch.int32 or not out.is_cuda or tuple(out.shape) != (ns, n) or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous ({ns}, {n}) int32 CUDA tensor")
+    o = opts("glynn", accum, flags=PH_FLAG_UNSORTED if unsorted else 0)
+    check(lib().ph_boson_sample(_ptr(u), m, u.stride(0), _i32p(ins), n, ns, _i32p(perms),
+                                uniforms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(out),
+                                ctypes.byref(o), _stream(u)))
+    return out
 
 
 def fp64_peak(iters: int = 1 << 14, device=None):

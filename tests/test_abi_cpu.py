@@ -67,7 +67,7 @@ def test_argument_errors_are_reported_before_any_device_work(L):
     assert _perm(L, fake, 10, 10, fake, P.PhOpts(7, 0, 0, 0, 0)) == P.PH_EINVAL
     assert _perm(L, fake, 10, 10, fake, P.PhOpts(0, 5, 0, 0, 0)) == P.PH_EINVAL
     assert _perm(L, fake, 10, 10, fake, P.PhOpts(0, 0, 0, 9, 0)) == P.PH_EINVAL
-    assert _perm(L, fake, 10, 10, fake, P.PhOpts(0, 0, 0, 0, 2)) == P.PH_EINVAL  # unknown flag bit
+    assert _perm(L, fake, 10, 10, fake, P.PhOpts(0, 0, 0, 0, 4)) == P.PH_EINVAL  # unknown flag bit
 
 
 def test_python_binding_rejects_non_device_tensors():
@@ -169,3 +169,41 @@ def test_partial_and_combine_argument_errors(L):
     assert comb(fake, -1, 10) == P.PH_EINVAL
     assert comb(None, 2, 10) == P.PH_EINVAL
     assert comb(fake, 1, 10, out=None) == P.PH_EINVAL
+
+
+def test_sampler_argument_errors_are_reported_before_any_device_work(L):
+    import numpy as np
+
+    from paper_1606_05836_amd import permhip as P
+
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    I32, F64 = ctypes.c_int32, ctypes.c_double
+
+    def sample(m, ins, perms, unis, ns=None, o=None, ldu=None, out=fake):
+        n = len(ins)
+        a = (I32 * max(1, n))(*ins)
+        pp = np.ascontiguousarray(np.asarray(perms, dtype=np.int32).reshape(-1))
+        uu = np.ascontiguousarray(np.asarray(unis, dtype=np.float64).reshape(-1))
+        ns = len(pp) // max(1, n) if ns is None else ns
+        return L.ph_boson_sample(fake, m, m if ldu is None else ldu, a, n, ns,
+                                 pp.ctypes.data_as(ctypes.POINTER(I32)), uu.ctypes.data_as(ctypes.POINTER(F64)),
+                                 out, ctypes.byref(o) if o else None, None)
+
+    ok_p, ok_u = [[0, 1], [1, 0]], [[0.1, 0.9], [0.0, 0.5]]
+    assert sample(4, [0, 0], ok_p, ok_u) == P.PH_EINVAL  # repeated input mode
+    assert b"repeats" in L.ph_last_error()
+    assert sample(4, [0, 4], ok_p, ok_u) == P.PH_EINVAL  # input mode >= m
+    assert sample(4, [0, 1], [[0, 0], [1, 0]], ok_u) == P.PH_EINVAL  # not a permutation
+    assert b"permutation" in L.ph_last_error()
+    assert sample(4, [0, 1], [[0, 2], [1, 0]], ok_u) == P.PH_EINVAL
+    assert sample(4, [0, 1], ok_p, [[0.1, 1.0], [0.0, 0.5]]) == P.PH_EINVAL  # uniform not below 1
+    assert sample(4, [0, 1], ok_p, [[0.1, float("nan")], [0.0, 0.5]]) == P.PH_EINVAL
+    assert sample(4, [0, 1], ok_p, [[-0.1, 0.2], [0.0, 0.5]]) == P.PH_EINVAL
+    assert sample(4, [0, 1], ok_p, ok_u, ldu=3) == P.PH_EINVAL
+    assert sample(4, [0, 1], ok_p, ok_u, ns=-1) == P.PH_EINVAL
+    assert sample(4, [0, 1], ok_p, ok_u, out=None) == P.PH_EINVAL
+    assert sample(4, [], [], []) == P.PH_EINVAL  # n >= 1
+    big = list(range(P.PH_NMAX_GRAD + 1))
+    assert sample(64, big, [big], [[0.5] * len(big)]) == P.PH_ERANGE
+    assert sample(4, [0, 1], ok_p, ok_u, o=P.PhOpts(P.PH_RYSER, 0, 0, 0, 0)) == P.PH_EINVAL
+    assert sample(4, [0, 1], ok_p, ok_u, ns=0) == P.PH_OK  # nothing to draw, nothing enqueued

@@ -1,0 +1,130 @@
+"""The chain-rule boson sampler (ph_boson_sample) against the exact oracle
+sampler on the same column orders and uniforms, against Eq. (1) in
+distribution, and at the full 900-mode, 30-photon workload step by step
+against the probability layer."""
+import math
+from collections import Counter
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import inputs as I
+import oracle as O
+from oracle import sampler as OS
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MARGIN = 1e-9  # relative distance of an exact decision from its boundary below which a case is not compared
+
+
+@pytest.fixture(scope="module")
+def ph():
+    import paper_1606_05836_amd as ph
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return ph
+
+
+def decided_clearly(trace, uniforms):
+    """Every step's target lies at least MARGIN * total away from the
+    boundaries of the chosen mode's interval."""
+    for (w, r), u in zip(trace, uniforms):
+        tot = sum(w)
+        t = Fraction(u) * tot
+        lo, hi = sum(w[:r]), sum(w[: r + 1])
+        if min(t - lo, hi - t) <= Fraction(MARGIN) * tot:
+            return False
+    return True
+
+
+def compare_with_oracle(ph, u, ins, ns, seed):
+    perms, unis = ph.sample_inputs(ns, len(ins), seed)
+    got = ph.boson_sample(torch.from_numpy(u).to("cuda"), ins, perms=perms, uniforms=unis).cpu().numpy()
+    compared = 0
+    for s in range(ns):
+        trace = []
+        want = OS.sample_exact(u, ins, tuple(int(x) for x in perms[s]), [float(x) for x in unis[s]], trace)
+        if decided_clearly(trace, unis[s]):
+            assert tuple(int(x) for x in got[s]) == want, s
+            compared += 1
+        assert list(got[s]) == sorted(got[s]) and all(0 <= x < u.shape[0] for x in got[s])
+    return compared
+
+
+def test_samples_match_oracle_small(ph):
+    u = I.haar(12, 3)
+    assert compare_with_oracle(ph, u, [0, 2, 5, 7], 64, 1) >= 60
+
+
+def test_samples_match_oracle_edge_sizes(ph):
+    assert compare_with_oracle(ph, I.haar(5, 4), [3], 16, 2) >= 15  # one photon: step 1 only
+    assert compare_with_oracle(ph, I.haar(4, 5), [0, 1, 2, 3], 16, 3) >= 15  # every mode an input
+    u = I.haar(40, 6)
+    assert compare_with_oracle(ph, u, [1, 5, 9, 13, 17, 21, 25, 29], 12, 4) >= 11
+
+
+def test_unsorted_is_the_placement_order_and_groups_split_cleanly(ph):
+    u = torch.from_numpy(I.haar(6, 7)).to("cuda")
+    ins = [0, 1, 2]
+    ns = 16384 + 37  # two groups
+    perms, unis = ph.sample_inputs(ns, 3, 8)
+    srt = ph.boson_sample(u, ins, perms=perms, uniforms=unis).cpu().numpy()
+    raw = ph.boson_sample(u, ins, perms=perms, uniforms=unis, unsorted=True).cpu().numpy()
+    assert np.array_equal(np.sort(raw, axis=1), srt)
+    tail = ph.boson_sample(u, ins, perms=perms[16384:], uniforms=unis[16384:]).cpu().numpy()
+    assert np.array_equal(tail, srt[16384:])
+    again = ph.boson_sample(u, ins, perms=perms, uniforms=unis).cpu().numpy()
+    assert np.array_equal(again, srt)  # deterministic
+    assert ph.boson_sample(u, ins, 0).shape == (0, 3)
+
+
+def test_distribution_matches_eq1(ph):
+    # 200k draws over the 56 outcomes of 3 photons in 6 modes against the exact
+    # Eq. (1) probabilities (smallest expected count 74): Pearson's statistic below the 0.9999 quantile of
+    # chi-square with 55 degrees of freedom (102.8; 110 allows for the
+    # residual non-unitarity of a binary64 Haar matrix), total variation < 0.005
+    m, ins, ns = 6, [0, 2, 3], 200_000
+    u = I.haar(m, 9)
+    p = {T: float(O.prob_exact(u, ins, T)) for T in __import__("itertools").combinations_with_replacement(range(m), 3)}
+    assert abs(sum(p.values()) - 1) < 1e-12
+    got = ph.boson_sample(torch.from_numpy(u).to("cuda"), ins, ns, seed=10).cpu().numpy()
+    cnt = Counter(tuple(int(x) for x in r) for r in got)
+    assert set(cnt) <= set(p)
+    chi2 = sum((cnt.get(T, 0) - ns * q) ** 2 / (ns * q) for T, q in p.items())
+    tv = 0.5 * sum(abs(cnt.get(T, 0) / ns - q) for T, q in p.items())
+    assert chi2 < 110, chi2
+    assert tv < 0.005, tv
+
+
+def test_full_workload_every_step_against_the_probability_layer(ph):
+    # 900 modes, 30 photons: for one sample, the 900 weights of every step are
+    # recomputed as Eq. (1) probabilities of the grown patterns (grouped sweeps,
+    # an independent path) times their occupation factorials; the sampler's
+    # choice must satisfy the decision rule with that step's uniform
+    u_np, ins, _ = I.config5_workload(m=900, n=30, patterns=1)
+    u = torch.from_numpy(u_np).to("cuda")
+    n = len(ins)
+    perms, unis = ph.sample_inputs(2, n, 11)
+    got = ph.boson_sample(u, ins, perms=perms, uniforms=unis, unsorted=True).cpu().numpy()
+    assert all(0 <= x < 900 for x in got.reshape(-1))
+    r = [int(x) for x in got[0]]
+    checked = 0
+    for k in range(1, n + 1):
+        cols = [int(ins[int(perms[0][l])]) for l in range(k)]
+        pats = np.array([r[: k - 1] + [i] for i in range(900)], dtype=np.int32)
+        pr = ph.boson_probs(u, cols, pats).cpu().numpy()
+        fact = np.array([math.prod(math.factorial(c) for c in Counter(row.tolist()).values()) for row in pats],
+                        dtype=np.float64)
+        w = pr * fact
+        cum = np.cumsum(w)
+        tot = cum[-1]
+        t = unis[0][k - 1] * tot
+        lo = cum[r[k - 1] - 1] if r[k - 1] > 0 else 0.0
+        hi = cum[r[k - 1]]
+        if min(t - lo, hi - t) > 1e-9 * tot:
+            assert lo <= t < hi, (k, r[k - 1], lo / tot, t / tot, hi / tot)
+            checked += 1
+    assert checked >= n - 1
