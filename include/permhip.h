@@ -196,6 +196,18 @@ int ph_boson_probs_grad(const ph_c128* U, int32_t m, int64_t ldu, const int32_t*
                         const int32_t* patterns, int64_t n_patterns, const double* weights, double* probs,
                         ph_c128* dU, int64_t lddu, const ph_opts* opt, void* stream);
 
+/* Minors along one row: for each of `batch` contiguous row-major n x (n+1)
+ * matrices B (device), minors[b][l] = Per(B without column l), l = 0..n, the
+ * derivatives of Per([B; x]) in the entries of an added last row x.  They
+ * come from differentiating Eq. (S2) of that (n+1) x (n+1) matrix in x: one
+ * Gray-code sweep of B's n rows over its n + 1 columns that adds every term,
+ * signed by delta_l, into one sum per column (n >= 12; smaller n go through
+ * the gradient sweep of ph_perm_grad).  The sampler below expands along x
+ * with them.  0 <= n <= PH_NMAX_GRAD - 1; minors (device, batch x (n+1)
+ * complex128); opt->algo must be PH_GLYNN. */
+int ph_perm_row_minors(const ph_c128* B, int32_t n, int64_t batch, ph_c128* minors, const ph_opts* opt,
+                       void* stream);
+
 /* Boson-sampling outputs, drawn by the chain rule over the output photons.
  * The paper's simulation serves sampling from main-text Eq. (1) but gives no
  * sampler; this is Clifford and Clifford's exact algorithm (2018).  With

@@ -19,6 +19,7 @@ from .permhip import (  # noqa: F401
     perm_partial,
     gray_terms,
     perm_grad,
+    perm_row_minors,
     version,
 )
 from . import segments  # noqa: F401

@@ -29,6 +29,9 @@
 
 namespace ph {
 
+int row_minors_launch(const double2* tabs, int n_rows, int64_t batch, double2* out, hipStream_t st, int cus);
+constexpr int MINORS_ROWS_MIN = 12;  // smaller steps take the gradient sweep
+
 constexpr int SAMPLE_THREADS = 256;
 constexpr int64_t SAMPLE_GROUP = 16384;  // samples per pass over the n steps
 
@@ -58,6 +61,23 @@ __global__ void k_sample_build(const double2* __restrict__ a, int n, const int32
   }
 }
 
+// BB/FG table of step k for sample s (k - 1 rows, k columns, column-major,
+// column stride k - 1): T[0] = A[rows, perm[0]], T[j] = -2 A[rows, perm[j]].
+__global__ void k_sample_tables(const double2* __restrict__ a, int n, const int32_t* __restrict__ perms,
+                                const int32_t* __restrict__ rows, int k, double2* __restrict__ tabs) {
+  const int64_t s = blockIdx.x;
+  const int32_t* pm = perms + s * n;
+  const int32_t* rw = rows + s * n;
+  const int nr = k - 1;
+  double2* out = tabs + s * (int64_t)nr * k;
+  for (int e = threadIdx.x; e < nr * k; e += blockDim.x) {
+    const int j = e / nr, i = e % nr;
+    double2 v = a[(int64_t)rw[i] * n + pm[j]];
+    if (j > 0) v = make_double2(-2.0 * v.x, -2.0 * v.y);
+    out[e] = v;
+  }
+}
+
 __device__ __forceinline__ double weight_of(const double2* __restrict__ ai, const int* cols, const double2* P,
                                             int k) {
   double re = 0.0, im = 0.0;
@@ -69,12 +89,14 @@ __device__ __forceinline__ double weight_of(const double2* __restrict__ ai, cons
   return re * re + im * im;
 }
 
-// Step k for sample s: the weights of all m modes and the choice.  grad is
-// the gradient output of the step's matrices (conj of the minors), NULL at
-// k = 1 where the only minor is the empty permanent 1.
+// Step k for sample s: the weights of all m modes and the choice.  The k
+// minors of sample s are minors[s * stride + off + l], conjugated when conj
+// is set (the gradient sweep writes conj(minor)); minors = NULL at k = 1,
+// where the only minor is the empty permanent 1.
 __global__ __launch_bounds__(SAMPLE_THREADS) void k_sample_step(const double2* __restrict__ a, int m, int n,
                                                                 const int32_t* __restrict__ perms,
-                                                                const double2* __restrict__ grad, int k,
+                                                                const double2* __restrict__ minors,
+                                                                int64_t stride, int64_t off, int conj, int k,
                                                                 const double* __restrict__ uniforms,
                                                                 int32_t* __restrict__ rows) {
   __shared__ double2 P[PH_NMAX_GRAD];
@@ -86,9 +108,9 @@ __global__ __launch_bounds__(SAMPLE_THREADS) void k_sample_step(const double2* _
   const int t = threadIdx.x;
   if (t < k) {
     cols[t] = perms[s * n + t];
-    if (grad) {
-      const double2 g = grad[s * (int64_t)k * k + (int64_t)(k - 1) * k + t];
-      P[t] = make_double2(g.x, -g.y);
+    if (minors) {
+      const double2 g = minors[s * stride + off + t];
+      P[t] = make_double2(g.x, conj ? -g.y : g.y);
     } else {
       P[t] = make_double2(1.0, 0.0);
     }
@@ -236,14 +258,25 @@ extern "C" int ph_boson_sample(const ph_c128* U, int32_t m, int64_t ldu, const i
     if ((rc = upload(st, d_perm, pc, 2))) return rc;
     const double* du = reinterpret_cast<const double*>(reinterpret_cast<char*>(d_perm) + align256((size_t)g * n * 4));
     for (int k = 1; k <= n; ++k) {
-      const double2* gr = nullptr;
-      if (k >= 2) {
+      const double2* mn = nullptr;
+      int64_t stride = 0, moff = 0;
+      int conj = 0;
+      if (k - 1 >= MINORS_ROWS_MIN) {
+        // minors along the last row only (the grad buffer holds the tables)
+        hipLaunchKernelGGL(k_sample_tables, dim3((unsigned)g), dim3(64), 0, st, d_a, n, d_perm, d_rows, k, d_grad);
+        if ((rc = row_minors_launch(d_grad, k - 1, g, d_mats, st, cus))) return rc;
+        mn = d_mats;
+        stride = k;
+      } else if (k >= 2) {
         hipLaunchKernelGGL(k_sample_build, dim3((unsigned)g), dim3(64), 0, st, d_a, n, d_perm, d_rows, k, d_mats);
         if ((rc = perm_grad_launch(d_mats, k, g, nullptr, nullptr, d_grad, o, st, cus))) return rc;
-        gr = d_grad;
+        mn = d_grad;
+        stride = (int64_t)k * k;
+        moff = (int64_t)(k - 1) * k;
+        conj = 1;
       }
-      hipLaunchKernelGGL(k_sample_step, dim3((unsigned)g), dim3(SAMPLE_THREADS), 0, st, d_a, m, n, d_perm, gr, k,
-                         du, d_rows);
+      hipLaunchKernelGGL(k_sample_step, dim3((unsigned)g), dim3(SAMPLE_THREADS), 0, st, d_a, m, n, d_perm, mn,
+                         stride, moff, conj, k, du, d_rows);
     }
     if (o.unsorted) {
       hipError_t e = hipMemcpyAsync(out_modes + s0 * n, d_rows, (size_t)g * n * 4, hipMemcpyDeviceToDevice, st);

@@ -25,7 +25,7 @@ PH_FLAG_UNGROUPED = 1
 PH_FLAG_UNSORTED = 2
 
 EXPORTS = ("ph_perm", "ph_perm_chunk_log2", "ph_perm_partial", "ph_perm_combine", "ph_perm_batched", "ph_plan_create", "ph_plan_execute", "ph_plan_destroy",
-           "ph_perm_grad", "ph_boson_probs", "ph_boson_probs_grad", "ph_boson_sample", "ph_fp64_peak", "ph_last_error",
+           "ph_perm_grad", "ph_perm_row_minors", "ph_boson_probs", "ph_boson_probs_grad", "ph_boson_sample", "ph_fp64_peak", "ph_last_error",
            "ph_version")
 
 
@@ -66,6 +66,7 @@ def lib() -> ctypes.CDLL:
     L.ph_boson_probs.argtypes = [vp, i32, i64, P(ctypes.c_int32), i32, P(ctypes.c_int32), i64, dp, op, vp]
     L.ph_boson_probs_grad.argtypes = [vp, i32, i64, P(ctypes.c_int32), i32, P(ctypes.c_int32), i64, dp, dp, vp,
                                       i64, op, vp]
+    L.ph_perm_row_minors.argtypes = [vp, i32, i64, vp, op, vp]
     L.ph_boson_sample.argtypes = [vp, i32, i64, P(ctypes.c_int32), i32, i64, P(ctypes.c_int32), P(ctypes.c_double),
                                   vp, op, vp]
     L.ph_fp64_peak.argtypes = [i64, P(ctypes.c_double), P(ctypes.c_double), vp]
@@ -341,6 +342,22 @@ def boson_probs_grad(u: torch.Tensor, in_modes, patterns, weights: torch.Tensor 
     check(lib().ph_boson_probs_grad(_ptr(u), m, u.stride(0), _i32p(ins), n, _i32p(pats), npat, _ptr(w),
                                     _ptr(probs), _ptr(du), du.stride(0), ctypes.byref(o), _stream(u)))
     return probs, du
+
+
+def perm_row_minors(b: torch.Tensor, accum="dd", out: torch.Tensor | None = None) -> torch.Tensor:
+    """Per of b without column l, for each l: b is (..., n, n+1) complex128 on
+    the GPU; the result is (..., n+1) (ph_perm_row_minors)."""
+    _need_c128_cuda("b", b)
+    if b.dim() < 2 or b.shape[-1] != b.shape[-2] + 1:
+        raise ValueError("b must be (..., n, n + 1)")
+    lead, n = b.shape[:-2], b.shape[-2]
+    count = int(np.prod(lead)) if len(lead) else 1
+    flat = b.reshape(count, n, n + 1).contiguous()
+    if out is None:
+        out = torch.empty(flat.shape[0], n + 1, dtype=torch.complex128, device=b.device)
+    o = opts("glynn", accum)
+    check(lib().ph_perm_row_minors(_ptr(flat), n, flat.shape[0], _ptr(out), ctypes.byref(o), _stream(b)))
+    return out.reshape(*lead, n + 1)
 
 
 def sample_inputs(nsamples: int, n: int, seed=None):
