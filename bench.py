@@ -332,6 +332,34 @@ def precision_allr(ph, dev):
     return rows
 
 
+def paper_n45(ph, dev, checkpoint_dir):
+    """The paper's 45 x 45 run: Per(diag(1+i)) = (1+i)^45 = -4194304 - 4194304i,
+    with both formulas over the whole Gray range, as checkpointed segments of
+    2^40 terms (one progress line each).  Returns seconds and exactness."""
+    import torch
+
+    import inputs
+    from paper_1606_05836_amd.segments import segmented_perm
+
+    a = torch.from_numpy(inputs.diag_matrix(45, 1 + 1j)).to(dev)
+    want = complex(-4194304, -4194304)
+    out = {}
+    for algo in ("glynn", "ryser"):
+        path = os.path.join(checkpoint_dir, f"n45_{algo}.json") if checkpoint_dir else None
+        if path and os.path.exists(path):
+            os.remove(path)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = segmented_perm(a, 40, checkpoint=path, algo=algo, progress=lambda m, al=algo: _log(f"n=45 {al}: {m}"))
+        per = r.total()
+        sec = time.perf_counter() - t0
+        terms = 1 << (44 if algo == "glynn" else 45)
+        _log(f"n=45 {algo}: {per} in {sec:.1f} s")
+        out[algo] = {"value": [per.real, per.imag], "exact": per == want, "seconds": sec,
+                     "terms_per_s": terms / sec, "segments": r.nseg_total, "slow_segments": r.slow}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -347,6 +375,9 @@ def main():
                     help="run one plain device copy of this size first (counter calibration)")
     ap.add_argument("--precision", default="", metavar="N,N",
                     help="print only the precision study, with these large sizes (e.g. 40,44)")
+    ap.add_argument("--paper-n45", action="store_true",
+                    help="print only the paper's 45 x 45 diag(1+i) run (both formulas, several minutes)")
+    ap.add_argument("--checkpoint-dir", default="", help="where --paper-n45 keeps its segment checkpoints")
     ap.add_argument("--grad-ratio", default="", metavar="N,N",
                     help="print only the gradient/forward cost ratio at these orders")
     ap.add_argument("--precision-allr", action="store_true",
@@ -372,6 +403,9 @@ def main():
     kw = dict(accum=args.accum, chunk_log2=args.chunk_log2, waves=args.waves)
     if args.precision_allr:
         print(json.dumps({"precision_allr": precision_allr(ph, dev)}), flush=True)
+        return
+    if args.paper_n45:
+        print(json.dumps({"paper_n45": paper_n45(ph, dev, args.checkpoint_dir)}), flush=True)
         return
     if args.grad_ratio:
         ns = [int(x) for x in args.grad_ratio.split(",") if x.strip()]

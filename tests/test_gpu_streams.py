@@ -24,8 +24,11 @@ def cuda(a):
 
 
 def run_all(ph, a, b, u, ins, pats):
+    n = a.shape[0]
+    perms, unis = ph.sample_inputs(8, len(ins), 3)
     return (ph.perm(a), ph.perm_batched(b), ph.perm_grad(b[:4])[1], ph.boson_probs(u, ins, pats),
-            ph.boson_probs_grad(u, ins, pats)[1])
+            ph.boson_probs_grad(u, ins, pats)[1], ph.perm_partial(a, 0, ph.gray_terms(n) // 2),
+            ph.perm_row_minors(b[:4, :15, :]), ph.boson_sample(u, ins, perms=perms, uniforms=unis))
 
 
 def test_side_stream_gives_the_same_bits(ph):
