@@ -145,7 +145,8 @@ int ph_perm_batched(const ph_c128* A_packed, const int64_t* offsets_host, const 
  * cached for this device), and records prep, sweep and finalize kernels in one
  * hipGraph.  ph_plan_execute replays the graph with the given input and output
  * (one hipGraphLaunch; the kernel arguments are updated in place when the
- * pointers differ from the last call).  A plan is bound to the device that
+ * pointers differ from the last call); matrices of order >= 45 (2^44 terms or
+ * more each) are then swept one at a time by the ph_perm kernels.  A plan is bound to the device that
  * was current at creation and may be used from one thread at a time. */
 int ph_plan_create(const int32_t* n_host, const int64_t* offsets_host, int64_t batch, const ph_opts* opt,
                    void* stream, void** plan);

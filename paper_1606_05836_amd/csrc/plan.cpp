@@ -58,7 +58,14 @@ struct PlanImpl {
   void* last_out = nullptr;
   hipStream_t last_stream = nullptr;
   bool launched = false;
+  // matrices of order >= SOLO_NMIN (and no caller-built tables) go through
+  // the one-matrix sweep after the graph, which splits each term over two
+  // lanes; the graph's finalize writes a placeholder that this overwrites
+  std::vector<int64_t> solo;
+  Opts opts;
 };
+
+constexpr int SOLO_NMIN = 45;
 
 template <typename T>
 static void push_arg(KernelNode& k, const T& v) {
@@ -358,6 +365,7 @@ int plan_build(const int32_t* n_host, const int64_t* off_host, int64_t batch, co
   hipGetDevice(&p->dev);
   p->algo = o.algo;
   p->plain = o.plain;
+  p->opts = o;
   p->batch = batch;
   p->n.assign(n_host, n_host + batch);
   p->ext_tables = ncols_host != nullptr;
@@ -435,7 +443,9 @@ int plan_build(const int32_t* n_host, const int64_t* off_host, int64_t batch, co
     m.out_index = b;
     tab_elems += table_elems(n);
     const int64_t first = (int64_t)items.size();
-    if (n > 0) {
+    const bool solo = !p->ext_tables && n >= SOLO_NMIN;
+    if (solo) p->solo.push_back(b);
+    if (n > 0 && !solo) {
       const int bk = bucket_of(n);
       const int nb = gray_bits(m.ncols, o.algo);
       const uint64_t nchunks = (uint64_t)1 << (nb - m.c);
@@ -520,6 +530,15 @@ int plan_exec(PlanImpl* p, const double2* a, double2* out, hipStream_t st) {
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   p->launched = true;
   p->last_stream = st;
+  if (!p->solo.empty()) {
+    const int cus = num_cus();
+    if (cus <= 0) return PH_EUNSUPPORTED;
+    for (int64_t b : p->solo) {
+      const int n = p->n[b];
+      const int rc = perm_single(a + p->off[b], n, n, out + b, p->opts, st, cus);
+      if (rc) return rc;
+    }
+  }
   return PH_OK;
 }
 

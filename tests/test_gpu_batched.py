@@ -143,3 +143,15 @@ def test_larger_size_buckets_exact(ph):
         re, im = re * zr - im * zi, re * zi + im * zr
     want = complex(float(re), float(im))
     assert abs(complex(got[3]) - want) <= 1e-14 * abs(want)
+
+
+@pytest.mark.skipif(__import__("os").environ.get("PH_LONG_TESTS") != "1",
+                    reason="a full n = 45 permanent takes about 2.5 minutes; set PH_LONG_TESTS=1")
+def test_batch_with_a_large_order_takes_the_two_lane_sweep(ph):
+    # orders >= 45 in a batch are swept one by one after the plan's graph (two
+    # lanes per term); the small ones stay in the graph
+    mats = [I.diag_matrix(45, 1 + 1j), gauss_int(6, 1), I.config3_matrix(20)]
+    got = ph.perm_batched([torch.from_numpy(m).to("cuda") for m in mats]).cpu().numpy()
+    assert complex(got[0]) == complex(-4194304, -4194304)
+    assert complex(got[1]) == O.to_complex(O.perm_exact(mats[1]))
+    assert O.rel_err(complex(got[2]), O.perm_exact(mats[2])) <= 1e-12
