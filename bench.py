@@ -121,6 +121,27 @@ def _event_ms(fn, reps, stream):
     return out
 
 
+def large_share(ph, dev, stream, n):
+    """One 2^37-term share of Per(A) at order n (A = n x n block of
+    Haar(1600, 31)), as device 3 of 8 would take it."""
+    import torch
+
+    import inputs
+
+    an = torch.from_numpy(inputs.config3_matrix(n)).to(dev)
+    total = 1 << (n - 1)
+    kb, m = 3 * (total // 8), 1 << 37
+    ph.perm_partial(an, kb, kb + (1 << 24))
+    ms = _median(_event_ms(lambda: ph.perm_partial(an, kb, kb + m), 1, stream))
+    tps = m / (ms / 1e3)
+    _log(f"share n={n}: {ms:.1f} ms for 2^37 terms, {tps:.3e} terms/s")
+    return {
+        "workload": f"terms [3 * 2^{n - 1} / 8, + 2^37) of Per(A), A = {n} x {n} block of Haar(1600, 31)",
+        "ms": ms, "terms_per_s": tps, "frac_fp64_peak": tps * flops_per_term(n) / 1e12 / PEAK_FP64_VECTOR_TFLOPS,
+        "projected_full_s_1gpu": total / tps, "projected_full_s_8gpu": total / tps / 8,
+    }
+
+
 def extras(ph, dev, stream):
     """Batched perms/s, the backward/forward ratio and the boson workload."""
     import numpy as np
@@ -161,20 +182,7 @@ def extras(ph, dev, stream):
     }
     # one device's share of the largest orders (two lanes per term), with
     # the full-sum time it implies on 1 and on 8 devices (a projection)
-    res["large_share"] = {}
-    for n in (48, 50):
-        an = torch.from_numpy(inputs.config3_matrix(n)).to(dev)
-        total = 1 << (n - 1)
-        kb, m = 3 * (total // 8), 1 << 37
-        ph.perm_partial(an, kb, kb + (1 << 24))
-        ms = _median(_event_ms(lambda: ph.perm_partial(an, kb, kb + m), 1, stream))
-        tps = m / (ms / 1e3)
-        _log(f"share n={n}: {ms:.1f} ms for 2^37 terms, {tps:.3e} terms/s")
-        res["large_share"][str(n)] = {
-            "workload": f"terms [3 * 2^{n - 1} / 8, + 2^37) of Per(A), A = {n} x {n} block of Haar(1600, 31)",
-            "ms": ms, "terms_per_s": tps, "frac_fp64_peak": tps * flops_per_term(n) / 1e12 / PEAK_FP64_VECTOR_TFLOPS,
-            "projected_full_s_1gpu": total / tps, "projected_full_s_8gpu": total / tps / 8,
-        }
+    res["large_share"] = {str(n): large_share(ph, dev, stream, n) for n in (48, 50)}
     # boson sampling: Eq. (1) probabilities and their gradient
     u, ins, pats = inputs.config5_workload()
     ud = torch.from_numpy(u).to(dev)
@@ -375,6 +383,8 @@ def main():
                     help="run one plain device copy of this size first (counter calibration)")
     ap.add_argument("--precision", default="", metavar="N,N",
                     help="print only the precision study, with these large sizes (e.g. 40,44)")
+    ap.add_argument("--large-share", type=int, default=0, metavar="N",
+                    help="print only one 2^37-term share of an order-N permanent")
     ap.add_argument("--paper-n45", action="store_true",
                     help="print only the paper's 45 x 45 diag(1+i) run (both formulas, several minutes)")
     ap.add_argument("--checkpoint-dir", default="", help="where --paper-n45 keeps its segment checkpoints")
@@ -403,6 +413,10 @@ def main():
     kw = dict(accum=args.accum, chunk_log2=args.chunk_log2, waves=args.waves)
     if args.precision_allr:
         print(json.dumps({"precision_allr": precision_allr(ph, dev)}), flush=True)
+        return
+    if args.large_share:
+        print(json.dumps({"large_share": {str(args.large_share): large_share(ph, dev, stream, args.large_share)}}),
+              flush=True)
         return
     if args.paper_n45:
         print(json.dumps({"paper_n45": paper_n45(ph, dev, args.checkpoint_dir)}), flush=True)
