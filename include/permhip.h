@@ -56,7 +56,9 @@ enum { PH_ACC_DD = 0, PH_ACC_PLAIN = 1 };
 #define PH_FLAG_UNGROUPED 1u
 #define PH_FLAG_UNSORTED 2u
 
-/* Options; pass NULL for the defaults (Glynn, double-double, tuned sizes).
+/* Options; pass NULL for the defaults (Glynn, double-double, tuned sizes; the
+ * environment variable PERMHIP_ACCUM=plain or =dd sets the default
+ * accumulation, any other value makes the call fail with PH_EINVAL).
  *   algo        PH_GLYNN or PH_RYSER
  *   accum       PH_ACC_DD or PH_ACC_PLAIN
  *   chunk_log2  log2 of the Gray-code chunk one lane walks between re-seeds

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -118,6 +119,14 @@ int workspace(hipStream_t st, size_t bytes, void** out) { return workspace_slot(
 
 int read_opts(const ph_opts* o, Opts* r) {
   Opts d;
+  if (!o) {
+    // defaults; PERMHIP_ACCUM=plain|dd overrides the accumulation
+    const char* acc = getenv("PERMHIP_ACCUM");
+    if (acc && *acc) {
+      if (!strcmp(acc, "plain")) d.plain = true;
+      else if (strcmp(acc, "dd")) return fail(PH_EINVAL, "PERMHIP_ACCUM=%s (plain or dd)", acc);
+    }
+  }
   if (o) {
     if (o->algo != PH_GLYNN && o->algo != PH_RYSER) return fail(PH_EINVAL, "opts.algo=%d", o->algo);
     if (o->accum != PH_ACC_DD && o->accum != PH_ACC_PLAIN) return fail(PH_EINVAL, "opts.accum=%d", o->accum);

@@ -226,3 +226,50 @@ def segmented_perm(a, segment_log2: int, checkpoint: str | None = None, algo="gl
                            gpu_combiner(a.device, n, algo, accum), checkpoint, shard, device_tag(a.device))
     r.run(max_segments, progress)
     return r
+
+
+def main(argv=None) -> int:
+    """Command line: Per of a matrix saved with numpy (.npy, complex, n x n)
+    as checkpointed segments on the current GPU; prints progress and a JSON
+    line.  Run it again with the same arguments to resume."""
+    import argparse
+
+    import numpy as np
+    import torch
+
+    ap = argparse.ArgumentParser(prog="python -m paper_1606_05836_amd.segments")
+    ap.add_argument("matrix", help=".npy file with an n x n complex matrix")
+    ap.add_argument("--segment-log2", type=int, default=40, help="log2 of the terms per segment (clamped)")
+    ap.add_argument("--checkpoint", default="", help="checkpoint file (resumed when it exists)")
+    ap.add_argument("--algo", default="glynn", choices=("glynn", "ryser"))
+    ap.add_argument("--accum", default="dd", choices=("dd", "plain"))
+    ap.add_argument("--shard", default="0/1", help="g/G: run shard g of G (the total needs all G)")
+    ap.add_argument("--max-segments", type=int, default=None, help="stop after this many new segments")
+    args = ap.parse_args(argv)
+    a_np = np.load(args.matrix, allow_pickle=False).astype(np.complex128)
+    if a_np.ndim != 2 or a_np.shape[0] != a_np.shape[1] or a_np.shape[0] < 1:
+        raise SystemExit("the matrix must be n x n with n >= 1")
+    g, G = (int(x) for x in args.shard.split("/"))
+    from . import permhip
+
+    n = a_np.shape[0]
+    c = permhip.perm_chunk_log2(n, args.algo, args.accum)
+    nb = n - 1 if args.algo == "glynn" else n
+    seg = max(c, min(args.segment_log2, nb))
+    a = torch.from_numpy(a_np).to("cuda")
+    r = segmented_perm(a, seg, args.checkpoint or None, args.algo, args.accum, shard=(g, G),
+                       max_segments=args.max_segments, progress=lambda m: print(m, flush=True))
+    out = {"n": n, "algo": args.algo, "accum": args.accum, "segment_log2": seg, "shard": [g, G],
+           "done": r.done, "next_segment": r.next_segment, "segments": [r.seg_begin, r.seg_end],
+           "seconds": sum(r.seconds), "slow_segments": r.slow}
+    if r.done and G == 1:
+        p = r.total()
+        out["permanent"] = [p.real, p.imag]
+    elif r.done:
+        out["partials"] = [[x.hex() for x in q] for q in r.partials]
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

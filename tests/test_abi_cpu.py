@@ -207,3 +207,20 @@ def test_sampler_argument_errors_are_reported_before_any_device_work(L):
     assert sample(64, big, [big], [[0.5] * len(big)]) == P.PH_ERANGE
     assert sample(4, [0, 1], ok_p, ok_u, o=P.PhOpts(P.PH_RYSER, 0, 0, 0, 0)) == P.PH_EINVAL
     assert sample(4, [0, 1], ok_p, ok_u, ns=0) == P.PH_OK  # nothing to draw, nothing enqueued
+
+
+def test_accumulation_default_from_the_environment(L, monkeypatch):
+    import ctypes as C
+
+    from paper_1606_05836_amd import permhip as P
+
+    c = C.c_int32(0)
+    for v in ("dd", "plain", ""):
+        monkeypatch.setenv("PERMHIP_ACCUM", v)
+        assert L.ph_perm_chunk_log2(20, None, C.byref(c)) == P.PH_OK
+    monkeypatch.setenv("PERMHIP_ACCUM", "quad")
+    assert L.ph_perm_chunk_log2(20, None, C.byref(c)) == P.PH_EINVAL
+    assert b"PERMHIP_ACCUM" in L.ph_last_error()
+    # explicit options do not read it
+    o = P.PhOpts(0, 0, 0, 0, 0)
+    assert L.ph_perm_chunk_log2(20, C.byref(o), C.byref(c)) == P.PH_OK

@@ -238,3 +238,32 @@ def test_ryser_diag_full_set_term(ph, n):
     assert complex(p[0] + p[1], p[2] + p[3]) == want
     p = ph.perm_partial(a, kb - 4 * L, kb, algo="ryser").cpu().tolist()
     assert p == [0.0, 0.0, 0.0, 0.0]
+
+
+def test_command_line_runs_and_resumes(ph, tmp_path):
+    import json
+    import os
+    import subprocess
+    import sys
+
+    n = 24
+    a = I.config3_matrix(n)
+    f = tmp_path / "a.npy"
+    np.save(f, a)
+    ck = tmp_path / "ck.json"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cmd = [sys.executable, "-m", "paper_1606_05836_amd.segments", str(f), "--segment-log2", "20",
+           "--checkpoint", str(ck)]
+    first = subprocess.run(cmd + ["--max-segments", "3"], cwd=root, capture_output=True, text=True, timeout=120)
+    assert first.returncode == 0, first.stderr
+    st = json.loads(first.stdout.strip().splitlines()[-1])
+    assert not st["done"] and st["next_segment"] == 3
+    second = subprocess.run(cmd, cwd=root, capture_output=True, text=True, timeout=120)
+    assert second.returncode == 0, second.stderr
+    lines = second.stdout.strip().splitlines()
+    assert sum(1 for x in lines if x.startswith("segment ")) == 5  # only the missing segments ran
+    out = json.loads(lines[-1])
+    assert out["done"]
+    per = complex(*out["permanent"])
+    whole = complex(ph.perm(cuda(a)).cpu())
+    assert abs(per - whole) <= 1e-15 * abs(whole)
