@@ -117,7 +117,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
         raise RuntimeError("sweep kernels spill registers: " + ", ".join(bad[:8]))
     objs = [os.path.join(OUT, u[0]) for u in us]
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-ldl"]
     p = subprocess.run(cmd, capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError("link failed:\n" + p.stdout + p.stderr)

@@ -694,6 +694,7 @@ using namespace ph;
 extern "C" int ph_boson_probs(const ph_c128* U, int32_t m, int64_t ldu, const int32_t* in_modes, int32_t n,
                               const int32_t* patterns, int64_t n_patterns, double* probs, const ph_opts* opt,
                               void* stream) {
+  PH_TRACE("ph_boson_probs");
   Opts o;
   int rc = read_opts(opt, &o);
   if (rc) return rc;
@@ -719,6 +720,7 @@ extern "C" int ph_boson_probs(const ph_c128* U, int32_t m, int64_t ldu, const in
 extern "C" int ph_boson_probs_grad(const ph_c128* U, int32_t m, int64_t ldu, const int32_t* in_modes, int32_t n,
                                    const int32_t* patterns, int64_t n_patterns, const double* weights, double* probs,
                                    ph_c128* dU, int64_t lddu, const ph_opts* opt, void* stream) {
+  PH_TRACE("ph_boson_probs_grad");
   Opts o;
   int rc = read_opts(opt, &o);
   if (rc) return rc;

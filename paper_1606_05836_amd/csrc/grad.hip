@@ -597,6 +597,7 @@ using namespace ph;
 
 extern "C" int ph_perm_grad(const ph_c128* A, int32_t n, int64_t batch, const ph_c128* grad_out, ph_c128* perm_out,
                             ph_c128* grad_A, const ph_opts* opt, void* stream) {
+  PH_TRACE("ph_perm_grad");
   Opts o;
   int rc = read_opts(opt, &o);
   if (rc) return rc;

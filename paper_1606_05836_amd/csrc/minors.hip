@@ -273,6 +273,7 @@ using namespace ph;
 
 extern "C" int ph_perm_row_minors(const ph_c128* B, int32_t n, int64_t batch, ph_c128* minors, const ph_opts* opt,
                                   void* stream) {
+  PH_TRACE("ph_perm_row_minors");
   Opts o;
   int rc = read_opts(opt, &o);
   if (rc) return rc;

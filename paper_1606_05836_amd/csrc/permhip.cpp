@@ -168,6 +168,7 @@ extern "C" const char* ph_last_error(void) { return t_err.c_str(); }
 extern "C" int ph_version(void) { return 10000; }
 
 extern "C" int ph_perm(const ph_c128* A, int32_t n, int64_t lda, ph_c128* out, const ph_opts* opt, void* stream) {
+  PH_TRACE("ph_perm");
   Opts o;
   int rc = read_opts(opt, &o);
   if (rc) return rc;
@@ -257,6 +258,7 @@ extern "C" int ph_perm_chunk_log2(int32_t n, const ph_opts* opt, int32_t* out) {
 
 extern "C" int ph_perm_partial(const ph_c128* A, int32_t n, int64_t lda, uint64_t k_begin, uint64_t k_end,
                                double* partial, const ph_opts* opt, void* stream) {
+  PH_TRACE("ph_perm_partial");
   Opts o;
   int rc = read_opts(opt, &o);
   if (rc) return rc;
@@ -293,6 +295,7 @@ extern "C" int ph_perm_partial(const ph_c128* A, int32_t n, int64_t lda, uint64_
 
 extern "C" int ph_perm_combine(const double* partials, int64_t count, int32_t n, ph_c128* out, const ph_opts* opt,
                                void* stream) {
+  PH_TRACE("ph_perm_combine");
   Opts o;
   int rc = read_opts(opt, &o);
   if (rc) return rc;

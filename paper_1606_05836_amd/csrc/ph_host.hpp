@@ -30,6 +30,16 @@ int min_chunk_log2(int nb);
 int pick_chunk_log2(int n, int algo, int requested);
 int perm_single(const double2* A, int n, int64_t lda, double2* out, const Opts& o, hipStream_t st, int cus);
 
+// rocTX range for the lifetime of the object when PERMHIP_ROCTX=1 (trace.cpp).
+struct TraceRange {
+  explicit TraceRange(const char* name);
+  ~TraceRange();
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+  bool on = false;
+};
+#define PH_TRACE(name) ::ph::TraceRange ph_trace_range_(name)
+
 // Host arrays copied to device memory in one transfer through a per-stream
 // pinned staging buffer (boson.hip): piece q lands at dst + the sum of the
 // previous pieces' sizes, each rounded up to 256 bytes.  Returns before the

@@ -565,6 +565,7 @@ using namespace ph;
 
 extern "C" int ph_plan_create(const int32_t* n_host, const int64_t* offsets_host, int64_t batch, const ph_opts* opt,
                               void* stream, void** plan) {
+  PH_TRACE("ph_plan_create");
   Opts o;
   int rc = read_opts(opt, &o);
   if (rc) return rc;
@@ -583,6 +584,7 @@ extern "C" int ph_plan_create(const int32_t* n_host, const int64_t* offsets_host
 }
 
 extern "C" int ph_plan_execute(void* plan, const ph_c128* A_packed, ph_c128* out, void* stream) {
+  PH_TRACE("ph_plan_execute");
   if (!plan) return fail(PH_EINVAL, "plan is NULL");
   auto* p = static_cast<PlanImpl*>(plan);
   if (p->batch > 0 && (!A_packed || !out)) return fail(PH_EINVAL, "A_packed or out is NULL");
@@ -622,6 +624,7 @@ constexpr size_t PLAN_CACHE = 4;
 
 extern "C" int ph_perm_batched(const ph_c128* A_packed, const int64_t* offsets_host, const int32_t* n_host,
                                int64_t batch, ph_c128* out, const ph_opts* opt, void* stream) {
+  PH_TRACE("ph_perm_batched");
   Opts o;
   int rc = read_opts(opt, &o);
   if (rc) return rc;

@@ -194,6 +194,7 @@ using namespace ph;
 extern "C" int ph_boson_sample(const ph_c128* U, int32_t m, int64_t ldu, const int32_t* in_modes, int32_t n,
                                int64_t nsamples, const int32_t* perms, const double* uniforms, int32_t* out_modes,
                                const ph_opts* opt, void* stream) {
+  PH_TRACE("ph_boson_sample");
   Opts o;
   int rc = read_opts(opt, &o);
   if (rc) return rc;

@@ -224,3 +224,23 @@ def test_accumulation_default_from_the_environment(L, monkeypatch):
     # explicit options do not read it
     o = P.PhOpts(0, 0, 0, 0, 0)
     assert L.ph_perm_chunk_log2(20, C.byref(o), C.byref(c)) == P.PH_OK
+
+
+def test_trace_ranges_switch_on_without_side_effects(L):
+    # PERMHIP_ROCTX=1 loads libroctx64 on the first traced call; the calls still
+    # validate and fail as before (read once per process, hence a subprocess)
+    import subprocess
+    import sys
+
+    code = (
+        "import ctypes, sys\n"
+        "sys.path.insert(0, %r)\n"
+        "from paper_1606_05836_amd import permhip as P\n"
+        "L = P.lib()\n"
+        "assert L.ph_perm(ctypes.c_void_p(0x1000), -1, 1, ctypes.c_void_p(0x1000), None, None) == P.PH_EINVAL\n"
+        "assert L.ph_perm_combine(None, -1, 10, ctypes.c_void_p(0x1000), None, None) == P.PH_EINVAL\n"
+        "print('ok')\n" % ROOT
+    )
+    env = dict(os.environ, PERMHIP_ROCTX="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and r.stdout.strip() == "ok", r.stderr
