@@ -81,3 +81,18 @@ def test_sampler_steps_through_row_minors_match_oracle(ph):
             assert tuple(int(x) for x in got[s]) == want, s
             compared += 1
     assert compared >= 2
+
+
+def test_plain_accumulation_and_batch_shapes(ph):
+    # the plain binary64 outer sum agrees with double-double to rounding, for
+    # both paths; leading batch dimensions come back as given
+    for n in (9, 16):
+        b = blocks(n, 6, 300 + n).reshape(2, 3, n, n + 1)
+        bt = torch.from_numpy(b).to("cuda")
+        dd = ph.perm_row_minors(bt)
+        pl = ph.perm_row_minors(bt, accum="plain")
+        assert dd.shape == (2, 3, n + 1)
+        big = dd.abs().max().item()
+        assert (dd - pl).abs().max().item() <= 1e-12 * big
+    with pytest.raises(ValueError):
+        ph.perm_row_minors(torch.zeros((3, 3), dtype=torch.complex128, device="cuda"))

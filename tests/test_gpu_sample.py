@@ -128,3 +128,13 @@ def test_full_workload_every_step_against_the_probability_layer(ph):
             assert lo <= t < hi, (k, r[k - 1], lo / tot, t / tot, hi / tot)
             checked += 1
     assert checked >= n - 1
+
+
+def test_plain_accumulation_gives_the_same_samples(ph):
+    # the weights differ only by rounding, so every clearly decided choice agrees
+    u = torch.from_numpy(I.haar(30, 14)).to("cuda")
+    ins = list(range(14))
+    perms, unis = ph.sample_inputs(32, 14, 15)
+    dd = ph.boson_sample(u, ins, perms=perms, uniforms=unis).cpu().numpy()
+    pl = ph.boson_sample(u, ins, perms=perms, uniforms=unis, accum="plain").cpu().numpy()
+    assert (dd == pl).all(axis=1).sum() >= 31
