@@ -64,6 +64,30 @@ __device__ __forceinline__ double2 dpp_mov(double2 v) {
   return make_double2(dpp_mov<CTRL>(v.x), dpp_mov<CTRL>(v.y));
 }
 constexpr int DPP_QUAD_XOR1 = 0xB1, DPP_QUAD_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141;
+constexpr int DPP_ROW_ROR4 = 0x124, DPP_ROW_ROR8 = 0x128;
+
+// group sums in registers (DPP and lane swaps) for the layouts where that is
+// faster than staging them through LDS: 4 lanes per term
+#ifndef PH_GRAD_GS_REG
+#define PH_GRAD_GS_REG(M, H) ((H) == 4)
+#endif
+
+// x plus the value of lane l ^ 16 (v_permlane16_swap exchanges the odd rows of
+// its first operand with the even rows of its second: with x in both, one
+// result holds the even rows' values and the other the odd rows', everywhere)
+__device__ __forceinline__ double plus_lane_xor16(double x) {
+  const unsigned lo = (unsigned)__double2loint(x), hi = (unsigned)__double2hiint(x);
+  const auto pl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto ph = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __hiloint2double((int)ph[0], (int)pl[0]) + __hiloint2double((int)ph[1], (int)pl[1]);
+}
+// x plus the value of lane l ^ 32 (likewise with the two halves)
+__device__ __forceinline__ double plus_lane_xor32(double x) {
+  const unsigned lo = (unsigned)__double2loint(x), hi = (unsigned)__double2hiint(x);
+  const auto pl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto ph = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double((int)ph[0], (int)pl[0]) + __hiloint2double((int)ph[1], (int)pl[1]);
+}
 
 // Stored columns (K) and target wavefronts per SIMD per (rows per lane M,
 // lanes per term H).
@@ -141,8 +165,39 @@ struct GradLane {
 // Sum of wt * W over the groups of the wavefront, through LDS.  Lane
 // o < 2 ROWS gets output o -- row o / 2 of the group's ROWS rows, real part
 // if o is even -- the other lanes get 0.
+// Group sums: wt * W summed over the NG groups, for each lane position in the
+// group and each of its rows; lane l < 2 ROWS returns entry group_index(l) of
+// an accumulator column (2 ROWS doubles: row r's real part at 2r, imaginary
+// at 2r + 1).  In registers, lane l holds component j = l / H of position
+// h = l % H (row h M + j / 2); through LDS, entry l.
 template <int M, int H>
-__device__ __forceinline__ double group_sum(const double2 (&W)[M], double wt, double* stage) {
+__device__ __forceinline__ int group_index(int lane) {
+  if constexpr (PH_GRAD_GS_REG(M, H)) return 2 * M * (lane % H) + lane / H;
+  return lane;
+}
+// x summed over the lanes that share lane mod H: rotations inside each
+// 16-lane row for the lane bits below 4, then across rows and halves
+template <int H>
+__device__ __forceinline__ double sum_over_groups(double x) {
+  if constexpr (H <= 4) x += dpp_mov<DPP_ROW_ROR4>(x);
+  if constexpr (H <= 8) x += dpp_mov<DPP_ROW_ROR8>(x);
+  return plus_lane_xor32(plus_lane_xor16(x));
+}
+template <int M, int H>
+__device__ __forceinline__ double group_sum_regs(const double2 (&W)[M], double wt) {
+  const int j = (threadIdx.x & 63) / H;
+  double s = 0.0;
+  static_for<0, 2 * M>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    // wt may differ between groups (the chunk-end terms take each chunk's own
+    // signs), so it scales every lane's values before they are summed
+    const double v = sum_over_groups<H>(wt * ((c & 1) ? W[c / 2].y : W[c / 2].x));
+    s = (j == c) ? v : s;
+  });
+  return s;
+}
+template <int M, int H>
+__device__ __forceinline__ double group_sum_lds(const double2 (&W)[M], double wt, double* stage) {
   using GS = GradShape<M, H>;
   constexpr int SS = GS::SS;
   const int lane = threadIdx.x & 63;
@@ -164,6 +219,11 @@ __device__ __forceinline__ double group_sum(const double2 (&W)[M], double wt, do
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   return s;
 }
+template <int M, int H>
+__device__ __forceinline__ double group_sum(const double2 (&W)[M], double wt, double* stage) {
+  if constexpr (PH_GRAD_GS_REG(M, H)) return group_sum_regs<M, H>(W, wt);
+  else return group_sum_lds<M, H>(W, wt, stage);
+}
 
 // Adds a group sum into the wavefront's accumulator column (global memory,
 // owned entry by entry by the lanes that compute them).
@@ -171,7 +231,7 @@ template <int M, int H>
 __device__ __forceinline__ void group_sum_add(const double2 (&W)[M], double wt, double* stage, double* gcol) {
   const double s = group_sum<M, H>(W, wt, stage);
   const int lane = threadIdx.x & 63;
-  if (lane < 2 * GradShape<M, H>::ROWS) gcol[lane] += s;
+  if (lane < 2 * GradShape<M, H>::ROWS) gcol[group_index<M, H>(lane)] += s;
 }
 
 // Product of the rows owned by the other H - 1 lanes of the group, from each
@@ -259,6 +319,7 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
   const int n = a.n, nc = a.ncols, c = a.c, nb = nc - 1;
   const int row0 = sig * M;
   const bool out_lane = lane < 2 * ROWS;
+  const int gidx = group_index<M, H>(lane);  // accumulator entry this lane owns
   for (;;) {
     if (threadIdx.x == 0) s_unit = (int64_t)atomicAdd(a.counter, 1u);
     __syncthreads();
@@ -272,7 +333,7 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
     double* ghat = reinterpret_cast<double*>(a.ghat + (size_t)slot * nc * ROWS);
     // each lane zeroes the accumulator entries it will own
     if (out_lane)
-      for (int j = 0; j < nc; ++j) ghat[j * 2 * ROWS + lane] = 0.0;
+      for (int j = 0; j < nc; ++j) ghat[j * 2 * ROWS + gidx] = 0.0;
     GradLane<M, H> L;
 #pragma unroll
     for (int b = 0; b < K; ++b)
@@ -389,7 +450,7 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
     if (out_lane) {
 #pragma unroll
       for (int q = 0; q < GS::R; ++q)
-        if (K + q + 1 < nc) ghat[(size_t)(K + q + 1) * 2 * ROWS + lane] += bacc[q];
+        if (K + q + 1 < nc) ghat[(size_t)(K + q + 1) * 2 * ROWS + gidx] += bacc[q];
     }
 #pragma unroll
     for (int b = 0; b < K; ++b)
