@@ -97,6 +97,8 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     def _uses_dpp(kernel):
         if "k_minors" in kernel:  # csrc/minors.hip keeps resident columns too
             return True
+        if "k_gradILi" in kernel:  # csrc/grad.hip: DPP and lane-swap exchanges every term
+            return True
         m = re.search(r"sweep_\w*?ILi(\d+)E(Li(\d+)E)?", kernel)
         if not m:
             return False
@@ -111,7 +113,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
 
     # kernels that read resident columns with DPP: no spill code of any kind
     # (AGPR copies included) is allowed there
-    bad = [k for k, v in report.items() if ("sweep" in k or "k_minors" in k) and _uses_dpp(k) and (
+    bad = [k for k, v in report.items() if ("sweep" in k or "k_minors" in k or "k_gradILi" in k) and _uses_dpp(k) and (
         v.get("VGPRs Spill", "0") != "0" or v.get("SGPRs Spill", "0") != "0" or v.get("AGPRs", "0") != "0")]
     if bad:
         raise RuntimeError("sweep kernels spill registers: " + ", ".join(bad[:8]))

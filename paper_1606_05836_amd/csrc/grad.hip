@@ -24,10 +24,11 @@
 //     that flip most often (Gray bits 0..K-1, used by 1 - 2^-K of all steps)
 //     are accumulated per lane in registers; a flip of any other column, and
 //     the boundary term of every column at the chunk end, is summed over the
-//     64/H groups of the wavefront through LDS (each lane adds 64/H values for
-//     one output) and added into the wavefront's n x ROWS accumulator in
-//     global memory.  Every address of that accumulator is read and written by
-//     one fixed lane only, so program order is the only ordering needed.
+//     64/H groups of the wavefront (a reduce-scatter across lanes, in
+//     registers) and added into the wavefront's n x ROWS
+//     accumulator in global memory.  Every address of that accumulator is read
+//     and written by one fixed lane only, so program order is the only
+//     ordering needed.
 //
 // The loop takes the terms in pairs (t, t+1), t even, with one copy of the
 // code for each: the step into t+1 always flips Gray bit 0, and the step into
@@ -64,29 +65,65 @@ __device__ __forceinline__ double2 dpp_mov(double2 v) {
   return make_double2(dpp_mov<CTRL>(v.x), dpp_mov<CTRL>(v.y));
 }
 constexpr int DPP_QUAD_XOR1 = 0xB1, DPP_QUAD_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141;
-constexpr int DPP_ROW_ROR4 = 0x124, DPP_ROW_ROR8 = 0x128;
 
-// group sums in registers (DPP and lane swaps) for the layouts where that is
-// faster than staging them through LDS: 4 lanes per term
-#ifndef PH_GRAD_GS_REG
-#define PH_GRAD_GS_REG(M, H) ((H) == 4)
-#endif
-
-// x plus the value of lane l ^ 16 (v_permlane16_swap exchanges the odd rows of
-// its first operand with the even rows of its second: with x in both, one
-// result holds the even rows' values and the other the odd rows', everywhere)
-__device__ __forceinline__ double plus_lane_xor16(double x) {
-  const unsigned lo = (unsigned)__double2loint(x), hi = (unsigned)__double2hiint(x);
-  const auto pl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-  const auto ph = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-  return __hiloint2double((int)ph[0], (int)pl[0]) + __hiloint2double((int)ph[1], (int)pl[1]);
+// One halving step of a reduce-scatter across lane bit B, for a pair of
+// values (x, y) held by every lane: the lanes on one side of bit B return
+// x + (partner's x), the others y + (partner's y).
+//  * B = 5, 4: v_permlane32_swap / v_permlane16_swap exchange the upper half
+//    (odd rows) of one operand with the lower half (even rows) of the other,
+//    so after the swap each lane holds its own value of the component its
+//    side keeps and its partner's, whichever operand order the hardware
+//    takes: the sum of the two results.
+//  * B = 3, 2: two bank-masked DPP moves within each 16-lane row (a bank is
+//    4 lanes; masked-off lanes keep the old value): the lanes with bit B
+//    clear read x from lane + 2^B (row_ror 8 or 12), the others y from
+//    lane - 2^B (row_ror 8 or 4).
+template <int B>
+__device__ __forceinline__ double pair_sum(double x, double y) {
+  if constexpr (B >= 4) {
+    const unsigned xl = (unsigned)__double2loint(x), xh = (unsigned)__double2hiint(x);
+    const unsigned yl = (unsigned)__double2loint(y), yh = (unsigned)__double2hiint(y);
+    if constexpr (B == 5) {
+      const auto l = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+      const auto h = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+      return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+    } else {
+      const auto l = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+      const auto h = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+      return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+    }
+  } else {
+    constexpr int UP = B == 3 ? 0x128 : 0x12C, DOWN = B == 3 ? 0x128 : 0x124;  // row_ror 8 / 12 / 4
+    constexpr int CLEAR = B == 3 ? 0x3 : 0x5, SET = B == 3 ? 0xC : 0xA;         // banks by bit B
+    const int xl = __double2loint(x), xh = __double2hiint(x);
+    const int yl = __double2loint(y), yh = __double2hiint(y);
+    // bit clear: partner's x (others keep y); bit set: partner's y (others keep x)
+    const double a = __hiloint2double(__builtin_amdgcn_update_dpp(yh, xh, UP, 0xF, CLEAR, false),
+                                      __builtin_amdgcn_update_dpp(yl, xl, UP, 0xF, CLEAR, false));
+    const double b = __hiloint2double(__builtin_amdgcn_update_dpp(xh, yh, DOWN, 0xF, SET, false),
+                                      __builtin_amdgcn_update_dpp(xl, yl, DOWN, 0xF, SET, false));
+    return a + b;
+  }
 }
-// x plus the value of lane l ^ 32 (likewise with the two halves)
-__device__ __forceinline__ double plus_lane_xor32(double x) {
-  const unsigned lo = (unsigned)__double2loint(x), hi = (unsigned)__double2hiint(x);
-  const auto pl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-  const auto ph = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-  return __hiloint2double((int)ph[0], (int)pl[0]) + __hiloint2double((int)ph[1], (int)pl[1]);
+
+// Reduce-scatter of C values per lane over lane bits B, B-1, ..., BLAST:
+// each step pairs value i with value i + ceil(C/2) (an unpaired middle value
+// with zero) and halves the count, so that every (lane mod 2^BLAST, value)
+// ends summed on exactly one lane; the other lanes end with 0.
+template <int C, int B, int BLAST, int CMAX>
+__device__ __forceinline__ double reduce_scatter(double (&v)[CMAX]) {
+  constexpr int HALF = (C + 1) / 2;
+  static_for<0, C / 2>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    v[i] = pair_sum<B>(v[i], v[i + HALF]);
+  });
+  if constexpr (C & 1) v[HALF - 1] = pair_sum<B>(v[HALF - 1], 0.0);
+  if constexpr (B == BLAST) {
+    static_assert(HALF == 1, "more values than the lane bits can spread");
+    return v[0];
+  } else {
+    return reduce_scatter<HALF, B - 1, BLAST>(v);
+  }
 }
 
 // Stored columns (K) and target wavefronts per SIMD per (rows per lane M,
@@ -135,10 +172,6 @@ struct GradShape {
   // they flip): at least the LOGP columns of the straight-line steps
   static constexpr int KR0 = PH_GRAD_KR(M, H) < K ? PH_GRAD_KR(M, H) : K;
   static constexpr int KR = KR0 > LOGP ? KR0 : LOGP;
-  // LDS staging: lane l writes its M complex values at complex offset l * SS,
-  // SS = M rounded up to odd, so the 16-byte writes of eight consecutive
-  // lanes cover all 32 banks once and the reads are conflict-free
-  static constexpr int SS = M | 1;
 };
 
 struct GradArgs {
@@ -162,76 +195,47 @@ struct GradLane {
   double2 colK[GradShape<M, H>::KR][M];  // the lane's rows of columns 1..KR
 };
 
-// Sum of wt * W over the groups of the wavefront, through LDS.  Lane
-// o < 2 ROWS gets output o -- row o / 2 of the group's ROWS rows, real part
-// if o is even -- the other lanes get 0.
 // Group sums: wt * W summed over the NG groups, for each lane position in the
-// group and each of its rows; lane l < 2 ROWS returns entry group_index(l) of
-// an accumulator column (2 ROWS doubles: row r's real part at 2r, imaginary
-// at 2r + 1).  In registers, lane l holds component j = l / H of position
-// h = l % H (row h M + j / 2); through LDS, entry l.
-template <int M, int H>
-__device__ __forceinline__ int group_index(int lane) {
-  if constexpr (PH_GRAD_GS_REG(M, H)) return 2 * M * (lane % H) + lane / H;
-  return lane;
-}
-// x summed over the lanes that share lane mod H: rotations inside each
-// 16-lane row for the lane bits below 4, then across rows and halves
+// group and each of its rows, into an accumulator column of 2 ROWS doubles
+// (row r's real part at 2r, imaginary at 2r + 1).  The 2M components of a
+// lane (value j: row h M + j / 2 of lane position h, real part if j is even)
+// are reduce-scattered over the lane bits above log2 H, so each entry ends on
+// one lane, the one for which group_slot gives its index; the other lanes
+// have slot -1.  wt may differ between groups (the chunk-end terms take each
+// chunk's own signs), so it scales every lane's values before they are summed.
 template <int H>
-__device__ __forceinline__ double sum_over_groups(double x) {
-  if constexpr (H <= 4) x += dpp_mov<DPP_ROW_ROR4>(x);
-  if constexpr (H <= 8) x += dpp_mov<DPP_ROW_ROR8>(x);
-  return plus_lane_xor32(plus_lane_xor16(x));
-}
+constexpr int log2_lanes() { return H == 4 ? 2 : 3; }
 template <int M, int H>
-__device__ __forceinline__ double group_sum_regs(const double2 (&W)[M], double wt) {
-  const int j = (threadIdx.x & 63) / H;
-  double s = 0.0;
-  static_for<0, 2 * M>([&](auto cc) {
-    constexpr int c = decltype(cc)::value;
-    // wt may differ between groups (the chunk-end terms take each chunk's own
-    // signs), so it scales every lane's values before they are summed
-    const double v = sum_over_groups<H>(wt * ((c & 1) ? W[c / 2].y : W[c / 2].x));
-    s = (j == c) ? v : s;
-  });
-  return s;
-}
-template <int M, int H>
-__device__ __forceinline__ double group_sum_lds(const double2 (&W)[M], double wt, double* stage) {
-  using GS = GradShape<M, H>;
-  constexpr int SS = GS::SS;
-  const int lane = threadIdx.x & 63;
-  double2* st2 = reinterpret_cast<double2*>(stage);
+__device__ __forceinline__ double group_sum(const double2 (&W)[M], double wt) {
+  double v[2 * M];
 #pragma unroll
-  for (int ii = 0; ii < M; ++ii) st2[lane * SS + ii] = make_double2(wt * W[ii].x, wt * W[ii].y);
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  double s = 0.0;
-  if (lane < 2 * GS::ROWS) {
-    const int sig = lane / (2 * M), d = lane % (2 * M);
-    const double* base = stage + 2 * sig * SS + d;
-#pragma unroll
-    for (int g = 0; g < GS::NG; ++g) s += base[2 * H * SS * g];
+  for (int i = 0; i < M; ++i) {
+    v[2 * i] = wt * W[i].x;
+    v[2 * i + 1] = wt * W[i].y;
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  return s;
+  return reduce_scatter<2 * M, 5, log2_lanes<H>()>(v);
 }
+// The slot of each lane, found by running the same exchanges on tags: value j
+// set to j + 1 on every lane sums to NG (j + 1) on the lane that receives
+// value j and to 0 elsewhere (all 64 lanes must be active).
 template <int M, int H>
-__device__ __forceinline__ double group_sum(const double2 (&W)[M], double wt, double* stage) {
-  if constexpr (PH_GRAD_GS_REG(M, H)) return group_sum_regs<M, H>(W, wt);
-  else return group_sum_lds<M, H>(W, wt, stage);
+__device__ __forceinline__ int group_slot(int lane) {
+  double v[2 * M];
+#pragma unroll
+  for (int j = 0; j < 2 * M; ++j) v[j] = (double)(j + 1);
+  const double s = reduce_scatter<2 * M, 5, log2_lanes<H>()>(v);
+  const int j = (int)(s / (64 / H)) - 1;
+  // only an exact tag names a slot, so no lane can write outside its column
+  const bool ok = j >= 0 && j < 2 * M && s == (double)((64 / H) * (j + 1));
+  return ok ? 2 * M * (lane % H) + j : -1;
 }
 
 // Adds a group sum into the wavefront's accumulator column (global memory,
-// owned entry by entry by the lanes that compute them).
+// owned entry by entry by the lanes that compute them; slot from group_slot).
 template <int M, int H>
-__device__ __forceinline__ void group_sum_add(const double2 (&W)[M], double wt, double* stage, double* gcol) {
-  const double s = group_sum<M, H>(W, wt, stage);
-  const int lane = threadIdx.x & 63;
-  if (lane < 2 * GradShape<M, H>::ROWS) gcol[group_index<M, H>(lane)] += s;
+__device__ __forceinline__ void group_sum_add(const double2 (&W)[M], double wt, double* gcol, int slot) {
+  const double s = group_sum<M, H>(W, wt);
+  if (slot >= 0) gcol[slot] += s;
 }
 
 // Product of the rows owned by the other H - 1 lanes of the group, from each
@@ -311,15 +315,13 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
   constexpr int K = GS::K, ROWS = GS::ROWS, NG = GS::NG;
   extern __shared__ double lds[];
   double2* tab = reinterpret_cast<double2*>(lds);  // ncols * ROWS complex
-  double* stage_all = lds + 2 * (size_t)a.ncols * ROWS;  // 4 waves * 64 * SS complex
   __shared__ int64_t s_unit;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sig = lane % H, grp = lane / H;
-  double* stage = stage_all + wave * 2 * 64 * GS::SS;
   const int n = a.n, nc = a.ncols, c = a.c, nb = nc - 1;
   const int row0 = sig * M;
-  const bool out_lane = lane < 2 * ROWS;
-  const int gidx = group_index<M, H>(lane);  // accumulator entry this lane owns
+  const int gidx = group_slot<M, H>(lane);  // accumulator entry this lane owns, or -1
+  const bool out_lane = gidx >= 0;
   for (;;) {
     if (threadIdx.x == 0) s_unit = (int64_t)atomicAdd(a.counter, 1u);
     __syncthreads();
@@ -397,7 +399,7 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
             });
           } else {
             if (b < K + GS::R) {
-              const double qs = group_sum<M, H>(L.W, 2.0 * sgu, stage);
+              const double qs = group_sum<M, H>(L.W, 2.0 * sgu);
               static_for<0, GS::R>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
                 if (b == K + q) {
@@ -406,7 +408,7 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
                 }
               });
             } else {
-              group_sum_add<M, H>(L.W, 2.0 * sgu, stage, ghat + (size_t)(b + 1) * 2 * ROWS);
+              group_sum_add<M, H>(L.W, 2.0 * sgu, ghat + (size_t)(b + 1) * 2 * ROWS, gidx);
             }
             grad_update<M, H>(L, sgu, tab + (b + 1) * ROWS + row0);
           }
@@ -432,10 +434,10 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
       // boundary terms delta_j(last) W(last) for every column
       const uint64_t kl = k0 + ((uint64_t)1 << c) - 1;
       const uint64_t gl = kl ^ (kl >> 1);
-      group_sum_add<M, H>(L.W, 1.0, stage, ghat);  // column 0: delta_0 = +1
+      group_sum_add<M, H>(L.W, 1.0, ghat, gidx);  // column 0: delta_0 = +1
 #pragma unroll 1
       for (int j = K + 1; j < nc; ++j)
-        group_sum_add<M, H>(L.W, ((gl >> (j - 1)) & 1) ? -1.0 : 1.0, stage, ghat + (size_t)j * 2 * ROWS);
+        group_sum_add<M, H>(L.W, ((gl >> (j - 1)) & 1) ? -1.0 : 1.0, ghat + (size_t)j * 2 * ROWS, gidx);
 #pragma unroll
       for (int b = 0; b < K; ++b) {
         const double dl = ((gl >> b) & 1) ? -1.0 : 1.0;
@@ -454,7 +456,7 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
     }
 #pragma unroll
     for (int b = 0; b < K; ++b)
-      if (b + 1 < nc) group_sum_add<M, H>(L.G[b], 1.0, stage, ghat + (size_t)(b + 1) * 2 * ROWS);
+      if (b + 1 < nc) group_sum_add<M, H>(L.G[b], 1.0, ghat + (size_t)(b + 1) * 2 * ROWS, gidx);
     if (sig != 0) acc = dd2{0.0, 0.0, 0.0, 0.0};
     acc = wave_reduce(acc, a.plain != 0);
     if (lane == 0) a.fparts[slot] = make_double4(acc.hr, acc.lr, acc.hi, acc.li);
@@ -589,7 +591,7 @@ int grad_sweep(const double2* tabs, int n, int ncols, int64_t batch, const doubl
   int c = o.chunk_log2 > 0 ? o.chunk_log2 : std::min(10, nb - need);
   c = std::max(K, std::min(c, nb));  // K >= LOGP, so a chunk holds whole runs
   const int64_t nsuper = (int64_t)((((uint64_t)1 << (nb - c)) + ng - 1) / ng);
-  const size_t lds = (size_t)ncols * rows * sizeof(double2) + 4 * 64 * (size_t)(lay.M | 1) * sizeof(double2);
+  const size_t lds = (size_t)ncols * rows * sizeof(double2);
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lay.kern, 256, lds);
   if (e != hipSuccess) return hip_fail(e, "occupancy");
