@@ -10,9 +10,10 @@ algorithmic FP64 rate against the chip's vector-FP64 peak, and the exact CPU
 oracle timed on a bounded sample of the same sweep on the host's cores.  The
 same line carries, under "extras", the other two figures of the metric --
 batched permanents/s (4096 matrices, n uniform in 16..26, one graph replay)
-and the backward/forward time ratio (1024 matrices of n = 20) -- and the
-boson-sampling workload (U 900 x 900, 30 photons, 256 collision patterns):
-probabilities/s and the gradient's cost.
+and the backward/forward time ratio (1024 matrices of n = 20) -- the latency
+of one small call (20 x 20 and 12 x 12), one 2^37-term share of n = 48 and
+n = 50, and the boson-sampling workload (U 900 x 900, 30 photons, 256
+collision patterns): probabilities/s, the gradient's cost and samples/s.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 40]
                        [--no-cpu] [--no-extras] [--copy-probe MiB]
@@ -143,13 +144,42 @@ def large_share(ph, dev, stream, n):
 
 
 def extras(ph, dev, stream):
-    """Batched perms/s, the backward/forward ratio and the boson workload."""
+    """Small-call latency, batched perms/s, the backward/forward ratio, the
+    largest orders' shares and the boson workload."""
     import numpy as np
     import torch
 
     import inputs
 
     res = {}
+    # latency of one small call: the 20 x 20 block of Haar(400, 11) read in
+    # place (lda = 400) and the 12 x 12 integer matrix; median of 100 calls
+    # after a warm-up, on the device (HIP events) and from the host (call to
+    # stream synchronised)
+    u1 = torch.from_numpy(inputs.haar(400, 11)).to(dev)
+    a1 = u1[:20, :20]
+    b1 = torch.from_numpy(inputs.config1_int12()).to(dev)
+    lat = {}
+    for name, m, algo, accum in (("haar20_glynn_dd", a1, "glynn", "dd"), ("haar20_glynn_plain", a1, "glynn", "plain"),
+                                 ("haar20_ryser_dd", a1, "ryser", "dd"), ("int12_glynn_dd", b1, "glynn", "dd")):
+        o1 = torch.empty((), dtype=torch.complex128, device=dev)
+
+        def call(m=m, algo=algo, accum=accum, o1=o1):
+            ph.perm(m, algo, accum, out=o1)
+
+        call()
+        torch.cuda.synchronize()
+        dev_ms = _median(_event_ms(call, 100, stream))
+        host = []
+        for _ in range(100):
+            t0 = time.perf_counter()
+            call()
+            stream.synchronize()
+            host.append(time.perf_counter() - t0)
+        lat[name] = {"device_us": dev_ms * 1e3, "host_us": _median(host) * 1e6}
+    _log("latency: " + ", ".join(f"{k} {v['device_us']:.0f} us ({v['host_us']:.0f} us host)" for k, v in lat.items()))
+    res["latency"] = {"workload": "one call: 20 x 20 block of Haar(400, 11) (lda 400); 12 x 12 integers in -3..3 "
+                                  "(seed 12); median of 100", **lat}
     # 4096 permanents, n ~ U{16..26}, one persistent graph replay
     ns, mats = inputs.config2_batch()
     flat = torch.from_numpy(np.concatenate([m.reshape(-1) for m in mats])).to(dev)

@@ -149,11 +149,14 @@ int gray_bits(int n, int algo) { return algo == PH_GLYNN ? n - 1 : n; }
 int min_chunk_log2(int nb) { return nb >= 4 ? 4 : (nb >= 1 ? 1 : 0); }
 
 // Chunk length: long enough to amortise the O(n^2) seed over the O(n) steps,
-// short enough to leave work for every lane and to bound row-sum drift.
+// short enough to leave work for every lane and to bound row-sum drift.  At
+// most 2^12 terms, and at least 2^17 chunks where the range allows: one per
+// lane of two 256-thread workgroups on each of 256 CUs, so that mid-size
+// orders fill the chip instead of a few CUs.
 int pick_chunk_log2(int n, int algo, int requested) {
   const int nb = gray_bits(n, algo);
   const int lo = min_chunk_log2(nb);
-  int c = requested > 0 ? requested : std::min(12, nb - 13);
+  int c = requested > 0 ? requested : std::min(12, nb - 17);
   return std::max(lo, std::min(c, nb));
 }
 

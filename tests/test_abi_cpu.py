@@ -122,10 +122,12 @@ def test_boson_argument_errors_are_reported_before_any_device_work(L):
 def test_chunk_length_query(L):
     from paper_1606_05836_amd import permhip as P
 
-    # default: 2^min(12, nb - 13) terms per chunk, at least 2^4 (2^1 for nb < 4), at most the whole sum
+    # default: 2^min(12, nb - 17) terms per chunk, at least 2^4 (2^1 for nb < 4), at most the whole sum
     assert P.perm_chunk_log2(40) == 12
-    assert P.perm_chunk_log2(20) == 6
-    assert P.perm_chunk_log2(20, "ryser") == 7
+    assert P.perm_chunk_log2(29) == 11  # 2^(28 - 11) = 2^17 chunks
+    assert P.perm_chunk_log2(26) == 8
+    assert P.perm_chunk_log2(26, "ryser") == 9
+    assert P.perm_chunk_log2(20) == 4  # the shortest chunk the sweeps take
     assert P.perm_chunk_log2(3) == 1
     assert P.perm_chunk_log2(1) == 0
     assert P.perm_chunk_log2(1, "ryser") == 1
