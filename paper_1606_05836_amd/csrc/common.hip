@@ -34,9 +34,11 @@ __global__ void k_reset(uint32_t* __restrict__ counters, int count) {
   if (i < count) counters[i] = 0;
 }
 
-// Fixed-order reduction of partials [begin, end) by one block: thread t sums a
-// contiguous slice in order, then thread 0 sums the slice totals in order.
-// The total is valid in thread 0 only.
+// Fixed-order reduction of partials [begin, end) by one block of a power-of-
+// two number of threads (at most 256): thread t sums a contiguous slice in
+// index order, then the slice totals are added in a fixed tree (slice t takes
+// slice t + s for s = nt/2, nt/4, ..., 1), so the result depends only on the
+// partials and the block size.  The total is returned to every thread.
 __device__ dd2 reduce_range(const double4* __restrict__ p, int64_t begin, int64_t end, int plain) {
   __shared__ dd2 part[256];
   const int t = threadIdx.x, nt = blockDim.x;
@@ -54,18 +56,18 @@ __device__ dd2 reduce_range(const double4* __restrict__ p, int64_t begin, int64_
   }
   part[t] = acc;
   __syncthreads();
-  dd2 s = part[0];
-  if (t == 0) {
-    for (int q = 1; q < nt; ++q) {
+  for (int s = nt / 2; s > 0; s >>= 1) {
+    if (t < s) {
       if (plain) {
-        s.hr += part[q].hr;
-        s.hi += part[q].hi;
+        part[t].hr += part[t + s].hr;
+        part[t].hi += part[t + s].hi;
       } else {
-        s = dd_add(s, part[q]);
+        part[t] = dd_add(part[t], part[t + s]);
       }
     }
+    __syncthreads();
   }
-  return s;
+  return part[0];
 }
 
 // The reduced sum, then the formula's scale: 2^-(n-1) (BB/FG, exact on both
