@@ -118,7 +118,8 @@ int ph_perm(const ph_c128* A, int32_t n, int64_t lda, ph_c128* out, const ph_opt
  * changes the rounding of the total, not its exactness bound.
  *
  * ph_perm_combine: out (device, one complex128) = the scaled sum of `count`
- * partials (device, 4 doubles each) added in index order, with the same
+ * partials (device, 4 doubles each) added in a fixed order (contiguous
+ * index-ordered slices, then a fixed tree over the slices), with the same
  * n and options (algo, accum) as the calls that made them.  Partials covering
  * the whole range [0, term count) give Per(A). */
 int ph_perm_chunk_log2(int32_t n, const ph_opts* opt, int32_t* out);
