@@ -5,23 +5,12 @@
 
 namespace ph {
 
-// Staging: builds the n-column table the sweep reads (see sweep.hpp):
-//   BB/FG  T[0] = a_{.,0},  T[j] = -2 a_{.,j} (j >= 1)
-//   Ryser  T[j] = a_{.,j}
-// stored column-major (column j is n contiguous complex entries).  Scaling by
-// -2 is exact, so the Gray step r_i += 2 delta_c(new) a_ic of Eq. (S2) is one
-// correctly rounded add per component.
+// Staging for the batched sweeps: the n-column table (table_entry in
+// sweep.hpp) of each matrix, stored column-major in the plan's table memory.
 __device__ __forceinline__ void prep_one(const double2* __restrict__ a, int64_t lda, int n, int algo,
                                          double2* __restrict__ tab, int e) {
   const int i = e / n, j = e % n;  // row-major read
-  double2 v = a[(int64_t)i * lda + j];
-  if (algo == ALGO_GLYNN && j >= 1) v = make_double2(-2.0 * v.x, -2.0 * v.y);
-  tab[(size_t)j * n + i] = v;
-}
-
-__global__ void k_prep(const double2* __restrict__ a, int64_t lda, int n, int algo, double2* __restrict__ tab) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n * n) prep_one(a, lda, n, algo, tab, e);
+  tab[(size_t)j * n + i] = table_entry(a, lda, algo, i, j);
 }
 
 __global__ void k_prep_batched(const MatDesc* __restrict__ mats, const double2* __restrict__ a_base, int algo) {
@@ -109,12 +98,6 @@ __global__ void k_finalize_batched(const MatDesc* __restrict__ mats, const doubl
                                    int plain, double2* __restrict__ out) {
   const MatDesc m = mats[blockIdx.x];
   finalize_range(p, m.part_begin, m.part_end, m.n, algo, plain, out + m.out_index);
-}
-
-void launch_prep(const double2* a, int64_t lda, int n, int algo, double2* tab, hipStream_t st) {
-  if (n <= 0) return;
-  const int tot = n * n;
-  hipLaunchKernelGGL(k_prep, dim3((tot + 255) / 256), dim3(256), 0, st, a, lda, n, algo, tab);
 }
 
 void launch_finalize_single(const double4* partials, int64_t nparts, int n, int algo, int plain, double2* out,

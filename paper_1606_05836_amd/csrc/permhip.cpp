@@ -190,8 +190,8 @@ extern "C" int ph_perm(const ph_c128* A, int32_t n, int64_t lda, ph_c128* out, c
 namespace ph {
 
 // Sweep the chunks [chunk0, chunk0 + nchunks) of length 2^c of one matrix:
-// the table is staged from A into the workspace, then one partial per wave is
-// written to the workspace; *parts and *nparts describe them.
+// every workgroup builds the table from A in its LDS, and one partial per wave
+// is written to the workspace; *parts and *nparts describe them.
 static int sweep_share(const double2* A, int n, int64_t lda, int c, uint64_t chunk0, uint64_t nchunks,
                        const Opts& o, hipStream_t st, int cus, double4** parts, int64_t* nparts) {
   hipError_t e;
@@ -208,18 +208,16 @@ static int sweep_share(const double2* A, int n, int64_t lda, int c, uint64_t chu
   blocks = std::min<uint64_t>(blocks, (nsuper + 3) / 4);
   blocks = std::max<uint64_t>(blocks, 1);
   const uint64_t nwaves = blocks * 4;
-  const size_t tab_bytes = table_elems(n) * sizeof(double2);
-  const size_t part_off = (tab_bytes + 255) & ~(size_t)255;
   void* ws = nullptr;
-  int rc = workspace(st, part_off + nwaves * sizeof(double4), &ws);
+  int rc = workspace(st, nwaves * sizeof(double4), &ws);
   if (rc) return rc;
-  double2* tab = reinterpret_cast<double2*>(ws);
-  double4* pw = reinterpret_cast<double4*>(reinterpret_cast<char*>(ws) + part_off);
-  launch_prep(A, lda, n, o.algo, tab, st);
+  double4* pw = reinterpret_cast<double4*>(ws);
+  const double2* a = A;
+  int64_t ld = lda;
   int cc = c;
   uint64_t ch0 = chunk0, nch = nchunks;
   int plain = o.plain ? 1 : 0;
-  void* args[] = {&tab, &cc, &ch0, &nch, &pw, &plain};
+  void* args[] = {&a, &ld, &cc, &ch0, &nch, &pw, &plain};
   e = hipLaunchKernel(kern, dim3((unsigned)blocks), dim3(256), args, lds, st);
   if (e != hipSuccess) return hip_fail(e, "sweep launch");
   *parts = pw;

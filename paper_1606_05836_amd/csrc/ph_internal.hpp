@@ -52,7 +52,6 @@ inline int bucket_of(int n) {
 }
 const void* batched_kernel(int bucket, int algo);
 
-void launch_prep(const double2* a, int64_t lda, int n, int algo, double2* tab, hipStream_t st);
 const void* prep_batched_kernel();      // k_prep_batched(mats, a_base, algo)
 const void* finalize_batched_kernel();  // k_finalize_batched(mats, partials, algo, plain, out)
 const void* reset_kernel();             // k_reset(counters, count)

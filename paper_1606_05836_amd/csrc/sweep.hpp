@@ -285,10 +285,25 @@ __device__ __forceinline__ dd2 wave_reduce(dd2 a, bool plain) {
   return a;
 }
 
-// Stage the n x n table into LDS (block-cooperative).
-template <int N>
-__device__ __forceinline__ void stage_table(double2* lds, const double2* __restrict__ tab) {
-  for (int e = threadIdx.x; e < N * N; e += blockDim.x) lds[e] = tab[e];
+// Entry (i, j) of the table the sweep reads, from A (row-major, leading
+// dimension lda):
+//   BB/FG  T[0] = a_{.,0},  T[j] = -2 a_{.,j} (j >= 1)
+//   Ryser  T[j] = a_{.,j}
+// Scaling by -2 is exact, so the Gray step r_i += 2 delta_c(new) a_ic of
+// Eq. (S2) is one correctly rounded add per component.
+__device__ __forceinline__ double2 table_entry(const double2* __restrict__ a, int64_t lda, int algo, int i, int j) {
+  const double2 v = a[(int64_t)i * lda + j];
+  return (algo == ALGO_GLYNN && j >= 1) ? make_double2(-2.0 * v.x, -2.0 * v.y) : v;
+}
+
+// Stage the n x n table into LDS straight from A, column-major (column j is
+// N contiguous entries); block-cooperative.
+template <int N, int ALGO>
+__device__ __forceinline__ void stage_table(double2* lds, const double2* __restrict__ a, int64_t lda) {
+  for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+    const int i = e / N, j = e % N;  // row-major reads
+    lds[j * N + i] = table_entry(a, lda, ALGO, i, j);
+  }
   __syncthreads();
 }
 

@@ -34,12 +34,12 @@ struct PairShape {
 };
 
 template <int N, int ALGO>
-__device__ __forceinline__ void stage_table_pair(double2* lds, const double2* __restrict__ tab) {
+__device__ __forceinline__ void stage_table_pair(double2* lds, const double2* __restrict__ a, int64_t lda) {
   using P = PairShape<N, ALGO>;
   for (int e = threadIdx.x; e < N * P::RS; e += blockDim.x) {
     const int j = e / P::RS, q = e % P::RS;
     double2 v = make_double2(0.0, 0.0);
-    if (q < N) v = tab[j * N + q];
+    if (q < N) v = table_entry(a, lda, ALGO, q, j);
     else if (ALGO == ALGO_GLYNN && j == 0) v = make_double2(1.0, 0.0);
     lds[e] = v;
   }

@@ -25,7 +25,7 @@
 namespace ph {
 
 template <int N, int ALGO>
-__global__ __launch_bounds__(256) void k_sweep_single(const double2* __restrict__ tab, int c, uint64_t chunk0,
+__global__ __launch_bounds__(256) void k_sweep_single(const double2* __restrict__ a, int64_t lda, int c, uint64_t chunk0,
                                                       uint64_t nchunks, double4* __restrict__ partials, int plain) {
   const int lane = threadIdx.x & 63;
   const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256) void k_sweep_single(const double2* __restrict_
     const uint64_t nsuper = (nchunks + 31) >> 5;
     const uint64_t s0 = nsuper * wave / nwaves;
     const uint64_t s1 = nsuper * (wave + 1) / nwaves;
-    stage_table_pair<N, ALGO>(lds_tab, tab);
+    stage_table_pair<N, ALGO>(lds_tab, a, lda);
     const double2* Tl = lds_tab + (upper ? PairShape<N, ALGO>::R : 0);
     ResidentPair<N, ALGO> res;
     res.load(Tl);
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void k_sweep_single(const double2* __restrict_
     const uint64_t nsuper = (nchunks + 63) >> 6;
     const uint64_t s0 = nsuper * wave / nwaves;
     const uint64_t s1 = nsuper * (wave + 1) / nwaves;
-    stage_table<N>(lds_tab, tab);
+    stage_table<N, ALGO>(lds_tab, a, lda);
     Resident<N, ALGO> res;
     res.load(lds_tab);
     for (uint64_t s = s0; s < s1; ++s) {
