@@ -267,3 +267,24 @@ def test_command_line_runs_and_resumes(ph, tmp_path):
     per = complex(*out["permanent"])
     whole = complex(ph.perm(cuda(a)).cpu())
     assert abs(per - whole) <= 1e-15 * abs(whole)
+
+
+@pytest.mark.parametrize("n", [1, 5, 16, 33, 44, 45, 52])
+@pytest.mark.parametrize("algo", ["glynn", "ryser"])
+def test_strided_rows_match_contiguous(ph, n, algo):
+    # every workgroup builds its table from A through lda: a view with row and
+    # column offsets inside a 64 x 64 parent (lda = 64) must give the bits of
+    # its contiguous copy, on the one-lane (n <= 44) and two-lane (n >= 45) sweeps
+    u = cuda(I.haar(64, 7))
+    view = u[3:3 + n, 5:5 + n]
+    assert view.stride(0) == 64
+    dense = view.contiguous()
+    L = 1 << ph.perm_chunk_log2(n, algo)
+    total = ph.gray_terms(n, algo)
+    kb = min(total // 3 // L * L, max(0, total - 64 * L))
+    ke = min(total, kb + 64 * L)
+    assert torch.equal(ph.perm_partial(view, kb, ke, algo=algo), ph.perm_partial(dense, kb, ke, algo=algo))
+    if n <= 16:
+        assert torch.equal(ph.perm(view, algo=algo), ph.perm(dense, algo=algo))
+    if n <= 5:
+        assert O.rel_err(complex(ph.perm(view, algo=algo).cpu()), O.perm_exact(view.cpu().numpy())) <= 1e-12
