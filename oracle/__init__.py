@@ -10,6 +10,7 @@ from .exact import (  # noqa: F401
     to_gaussian_integers,
     perm_brute_int,
     ryser_subsets_int,
+    ryser_paired_int,
     ryser_gray_raw,
     glynn_direct_raw,
     glynn_gray_raw,

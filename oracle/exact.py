@@ -17,7 +17,9 @@ What it computes (and from which passage of the paper):
   Eq. (S1): Per(A) = (-1)^n sum_{S subset of columns} (-1)^{|S|}
   prod_i sum_{j in S} a_ij.  ``ryser_subsets`` evaluates it in plain subset
   order, each subset's row sums formed from scratch (the original
-  O(n^2 2^n) order the paper ran).
+  O(n^2 2^n) order the paper ran).  ``ryser_paired_int`` takes the load-
+  balanced order of Algorithm S3: half the subsets, each with its
+  complement.
 
 * BB/FG (Glynn) formula, same section, Eq. (S2): Per(A) =
   [sum_delta (prod_k delta_k) prod_i sum_j delta_j a_ij] / 2^(n-1), with
@@ -149,6 +151,35 @@ def ryser_subsets_int(g):
         else:
             re += p[0]
             im += p[1]
+    if n % 2:
+        re, im = -re, -im
+    return re, im
+
+
+def ryser_paired_int(g):
+    """Ryser's formula with the load balance of Supplementary Algorithm S3 on
+    a Gaussian-integer matrix: the loop index it runs over [0, 2^(n-1)), bit
+    i of it puts column i (of the first n - 1) in S, and each S contributes
+    its own term of Eq. (S1) and the term of its complement S_C among all n
+    columns -- so every subset of the n columns appears exactly once, and
+    every iteration costs the same.  Row sums from scratch, as in the loop;
+    returns Per as an int pair."""
+    n = len(g)
+    if n == 0:
+        return 1, 0
+    re = im = 0
+    for it in range(1 << (n - 1)):
+        s = [j for j in range(n - 1) if (it >> j) & 1]
+        s_c = [j for j in range(n) if j not in s]
+        for cols in (s, s_c):
+            rowsums = [(sum(g[i][j][0] for j in cols), sum(g[i][j][1] for j in cols)) for i in range(n)]
+            p = _prod(rowsums)
+            if len(cols) % 2:
+                re -= p[0]
+                im -= p[1]
+            else:
+                re += p[0]
+                im += p[1]
     if n % 2:
         re, im = -re, -im
     return re, im
@@ -302,7 +333,8 @@ def perm_exact(a, method: str = "glynn"):
     """Exact permanent of ``a`` as an (re, im) pair of Fractions.
 
     method: "glynn" (Eq. (S2), Gray order), "glynn_direct", "ryser" (Eq. (S1),
-    plain subset order) or "brute" (the definition).
+    plain subset order), "ryser_paired" (Eq. (S1) with the complement pairing
+    of Algorithm S3) or "brute" (the definition).
     """
     g, d = to_gaussian_integers(a)
     n = len(g)
@@ -319,6 +351,8 @@ def perm_exact(a, method: str = "glynn"):
             r = (raw[0] // div, raw[1] // div)
     elif method == "ryser":
         r = ryser_subsets_int(g)
+    elif method == "ryser_paired":
+        r = ryser_paired_int(g)
     elif method == "brute":
         r = perm_brute_int(g)
     else:

@@ -44,6 +44,7 @@ def test_four_routes_agree_on_gaussian_integers(n, seed):
     ref = O.perm_exact(a, "brute")
     assert O.perm_exact(a, "glynn") == ref
     assert O.perm_exact(a, "ryser") == ref
+    assert O.perm_exact(a, "ryser_paired") == ref
     if n > 0:
         assert O.perm_exact(a, "glynn_direct") == ref
 
@@ -244,6 +245,25 @@ def test_ryser_gray_range_split_and_closed_form():
     for n in range(1, 8):
         ones = [[(1, 0)] * n for _ in range(n)]
         assert O.ryser_gray_raw(ones) == ((-1) ** n * math.factorial(n), 0)
+
+
+@pytest.mark.parametrize("n", range(1, 8))
+def test_ryser_paired_algorithm_s3(n):
+    # Algorithm S3's pairing: S over the subsets of the first n - 1 columns,
+    # S_C its complement among all n, covers every subset exactly once
+    seen = set()
+    for it in range(1 << (n - 1)):
+        seen.update((it, ((1 << n) - 1) ^ it))
+    assert len(seen) == 1 << n
+    ones = [[(1, 0)] * n for _ in range(n)]
+    assert O.ryser_paired_int(ones) == (math.factorial(n), 0)
+    diag = [[(j + 2, 1 - j) if i == j else (0, 0) for j in range(n)] for i in range(n)]
+    want = (1, 0)
+    for j in range(n):
+        want = (want[0] * (j + 2) - want[1] * (1 - j), want[0] * (1 - j) + want[1] * (j + 2))
+    assert O.ryser_paired_int(diag) == want
+    g, _ = O.to_gaussian_integers(gauss_int_matrix(n, 700 + n))
+    assert O.ryser_paired_int(g) == O.perm_brute_int(g)
 
 
 # ------------------------------------------------------ values the paper prints
