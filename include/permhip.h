@@ -95,6 +95,17 @@ enum {
  * chunks, one per GPU lane at a time; see the formulas above. */
 int ph_perm(const ph_c128* A, int32_t n, int64_t lda, ph_c128* out, const ph_opts* opt, void* stream);
 
+/* ph_perm_ryser_paired: *out (device, one complex128) = Per(A) by Ryser's
+ * formula, Eq. (S1), in the load-balanced order of Supplementary
+ * Algorithm S3: the loop runs over the 2^(n-1) subsets S of the first n - 1
+ * columns (in Gray order here) and takes with each S the term of its
+ * complement among all n columns, so every subset is summed once.  A as
+ * ph_perm (device, lda >= n), 0 <= n <= 32.  opt: accum and chunk_log2 are
+ * used (algo and waves are ignored; a chunk is 2^chunk_log2 loop indices).
+ * Errors: PH_EINVAL (NULL pointer, lda < n, n < 0, bad options), PH_ERANGE
+ * (n > 32), PH_EHIP.  Asynchronous on `stream`; deterministic. */
+int ph_perm_ryser_paired(const ph_c128* A, int32_t n, int64_t lda, ph_c128* out, const ph_opts* opt, void* stream);
+
 /* One share of a permanent's Gray-code sum, for sums split across devices or
  * run as resumable segments.  The parallel listings of the Supplementary
  * (Algorithms S1 and S2) give each process a contiguous range of the term

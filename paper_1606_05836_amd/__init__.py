@@ -20,6 +20,7 @@ from .permhip import (  # noqa: F401
     gray_terms,
     perm_grad,
     perm_row_minors,
+    perm_ryser_paired,
     version,
 )
 from . import segments  # noqa: F401

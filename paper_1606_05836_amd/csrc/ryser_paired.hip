@@ -1,0 +1,170 @@
+// Ryser's formula with the complement pairing of Supplementary Algorithm S3
+// (gfx950), one lane per chunk of the pairing loop.
+//
+// Eq. (S1) sums over all 2^n column subsets S.  Algorithm S3 runs its loop
+// over the subsets S of the first n - 1 columns only and takes with each the
+// term of its complement S_C among all n columns, so every subset is summed
+// once and every iteration does the same work.  Here the loop index k in
+// [0, 2^(n-1)) is walked in reflected Gray order (S = the set bits of
+// k XOR (k >> 1)): each lane takes a chunk of 2^c consecutive indices, seeds
+// its row sums r_i(S) at the chunk start and updates them by one column per
+// step.  The complement's row sums are T_i - r_i(S), T_i the full row sums
+// (computed once per workgroup, in column order), and the pair contributes
+//     (-1)^|S| [ prod_i r_i(S) + (-1)^n prod_i (T_i - r_i(S)) ],
+// where (-1)^|S| = (-1)^k.  The chunk sums go through the per-wave partials
+// and the fixed-order finalize of the one-matrix sweeps, which apply the
+// formula's (-1)^n.
+//
+// The row totals are read from LDS at every term (4n more VGPRs would not
+// leave room at n = 32), so this walk does the work of the plain Ryser sweep
+// plus n complex subtractions per term, with half the Gray steps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <utility>
+
+#include "dd.hpp"
+#include "permhip.h"
+#include "ph_host.hpp"
+#include "ph_internal.hpp"
+#include "sweep.hpp"
+
+namespace ph {
+
+constexpr int PAIRED_NMAX = 32;
+
+template <int N>
+__global__ __launch_bounds__(256) void k_ryser_paired(const double2* __restrict__ a, int64_t lda, int c,
+                                                      uint64_t nchunks, double4* __restrict__ partials, int plain) {
+  extern __shared__ double2 lds_paired[];
+  double2* col = lds_paired;          // column j of A at col + j * N
+  double2* tot = lds_paired + N * N;  // row totals T_i
+  for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+    const int i = e / N, j = e % N;
+    col[j * N + i] = a[(int64_t)i * lda + j];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int j = 0; j < N; ++j) {
+      s.x += col[j * N + i].x;
+      s.y += col[j * N + i].y;
+    }
+    tot[i] = s;
+  }
+  __syncthreads();
+  const double sgn_c = (N & 1) ? -1.0 : 1.0;  // (-1)^|S_C| = (-1)^n (-1)^|S|
+  const uint64_t lanes = (uint64_t)gridDim.x * blockDim.x;
+  const uint32_t len = 1u << c;
+  dd2 acc = {0.0, 0.0, 0.0, 0.0};
+  for (uint64_t ch = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; ch < nchunks; ch += lanes) {
+    const uint64_t k0 = ch << c;
+    uint64_t g = k0 ^ (k0 >> 1);
+    double2 r[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) r[i] = make_double2(0.0, 0.0);
+#pragma unroll 1
+    for (int j = 0; j < N - 1; ++j) {
+      if ((g >> j) & 1) {
+        const double2* cj = col + j * N;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          r[i].x += cj[i].x;
+          r[i].y += cj[i].y;
+        }
+      }
+    }
+    double2 sb = make_double2(0.0, 0.0);
+    for (uint32_t t = 0; t < len; ++t) {
+      if (t != 0) {
+        // the step into index k0 + t flips bit b = ctz(t) of the Gray word
+        // (k0 is a multiple of the chunk length): column b joins S or leaves it
+        const int b = __builtin_ctz(t);
+        g ^= (uint64_t)1 << b;
+        const double w = ((g >> b) & 1) ? 1.0 : -1.0;
+        const double2* cb = col + b * N;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          r[i].x = fma(w, cb[i].x, r[i].x);
+          r[i].y = fma(w, cb[i].y, r[i].y);
+        }
+      }
+      double2 p = r[0];
+      double2 q = make_double2(tot[0].x - r[0].x, tot[0].y - r[0].y);
+#pragma unroll
+      for (int i = 1; i < N; ++i) {
+        p = cmul(p, r[i]);
+        q = cmul(q, make_double2(tot[i].x - r[i].x, tot[i].y - r[i].y));
+      }
+      const double s = ((k0 + t) & 1) ? -1.0 : 1.0;  // (-1)^|S|
+      sb.x = fma(s, fma(sgn_c, q.x, p.x), sb.x);
+      sb.y = fma(s, fma(sgn_c, q.y, p.y), sb.y);
+      if (((t + 1) & 15) == 0 || t + 1 == len) flush(acc, sb, plain != 0, true);
+    }
+  }
+  acc = wave_reduce(acc, plain != 0);
+  const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if ((threadIdx.x & 63) == 0) partials[wave] = make_double4(acc.hr, acc.lr, acc.hi, acc.li);
+}
+
+template <int... Is>
+static const void* paired_lookup(int n, std::integer_sequence<int, Is...>) {
+  const void* out = nullptr;
+  ((n == Is + 1 ? (out = (const void*)&k_ryser_paired<Is + 1>, 0) : 0), ...);
+  return out;
+}
+
+static int perm_ryser_paired(const double2* A, int n, int64_t lda, double2* out, const Opts& o, hipStream_t st,
+                             int cus) {
+  hipError_t e;
+  const int plain = o.plain ? 1 : 0;
+  if (n == 0) {
+    launch_finalize_single(nullptr, 0, 0, ALGO_RYSER, plain, out, st);
+    e = hipGetLastError();
+    return e == hipSuccess ? PH_OK : hip_fail(e, "finalize launch");
+  }
+  const void* kern = paired_lookup(n, std::make_integer_sequence<int, PAIRED_NMAX>{});
+  if (!kern) return fail(PH_ERANGE, "no paired Ryser kernel for n=%d", n);
+  // loop indices [0, 2^(n-1)) in chunks of 2^c: at least 2^17 chunks where
+  // the range allows, at most 2^10 indices per chunk
+  const int nb = n - 1;
+  int c = o.chunk_log2 > 0 ? o.chunk_log2 : std::min(10, nb - 17);
+  c = std::max(0, std::min(c, nb));
+  const uint64_t nchunks = (uint64_t)1 << (nb - c);
+  const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>((nchunks + 255) / 256, (uint64_t)cus * 2));
+  const uint64_t nwaves = blocks * 4;
+  void* ws = nullptr;
+  int rc = workspace(st, nwaves * sizeof(double4), &ws);
+  if (rc) return rc;
+  double4* pw = static_cast<double4*>(ws);
+  const size_t lds = (size_t)(n * n + n) * sizeof(double2);
+  const double2* a = A;
+  int64_t ld = lda;
+  uint64_t nch = nchunks;
+  int cc = c, pl = plain;
+  void* args[] = {&a, &ld, &cc, &nch, &pw, &pl};
+  e = hipLaunchKernel(kern, dim3((unsigned)blocks), dim3(256), args, lds, st);
+  if (e != hipSuccess) return hip_fail(e, "paired Ryser launch");
+  launch_finalize_single(pw, (int64_t)nwaves, n, ALGO_RYSER, plain, out, st);
+  e = hipGetLastError();
+  return e == hipSuccess ? PH_OK : hip_fail(e, "finalize launch");
+}
+
+}  // namespace ph
+
+using namespace ph;
+
+extern "C" int ph_perm_ryser_paired(const ph_c128* A, int32_t n, int64_t lda, ph_c128* out, const ph_opts* opt,
+                                    void* stream) {
+  PH_TRACE("ph_perm_ryser_paired");
+  Opts o;
+  int rc = read_opts(opt, &o);
+  if (rc) return rc;
+  if (n < 0) return fail(PH_EINVAL, "n=%d < 0", n);
+  if (n > PAIRED_NMAX) return fail(PH_ERANGE, "n=%d > %d (the paired walk keeps n row sums per lane)", n, PAIRED_NMAX);
+  if (!out) return fail(PH_EINVAL, "out is NULL");
+  if (n > 0 && !A) return fail(PH_EINVAL, "A is NULL");
+  if (n > 0 && lda < n) return fail(PH_EINVAL, "lda=%lld < n=%d", (long long)lda, n);
+  return perm_ryser_paired(reinterpret_cast<const double2*>(A), n, lda, reinterpret_cast<double2*>(out), o,
+                           (hipStream_t)stream, num_cus());
+}

@@ -24,7 +24,7 @@ PH_NMAX, PH_NMAX_GRAD = 52, 32
 PH_FLAG_UNGROUPED = 1
 PH_FLAG_UNSORTED = 2
 
-EXPORTS = ("ph_perm", "ph_perm_chunk_log2", "ph_perm_partial", "ph_perm_combine", "ph_perm_batched", "ph_plan_create", "ph_plan_execute", "ph_plan_destroy",
+EXPORTS = ("ph_perm", "ph_perm_ryser_paired", "ph_perm_chunk_log2", "ph_perm_partial", "ph_perm_combine", "ph_perm_batched", "ph_plan_create", "ph_plan_execute", "ph_plan_destroy",
            "ph_perm_grad", "ph_perm_row_minors", "ph_boson_probs", "ph_boson_probs_grad", "ph_boson_sample", "ph_fp64_peak", "ph_last_error",
            "ph_version")
 
@@ -55,6 +55,7 @@ def lib() -> ctypes.CDLL:
     op = ctypes.POINTER(PhOpts)
     P = ctypes.POINTER
     L.ph_perm.argtypes = [vp, i32, i64, vp, op, vp]
+    L.ph_perm_ryser_paired.argtypes = [vp, i32, i64, vp, op, vp]
     L.ph_perm_chunk_log2.argtypes = [i32, op, P(ctypes.c_int32)]
     L.ph_perm_partial.argtypes = [vp, i32, i64, ctypes.c_uint64, ctypes.c_uint64, vp, op, vp]
     L.ph_perm_combine.argtypes = [vp, i64, i32, vp, op, vp]
@@ -130,6 +131,25 @@ def perm(a: torch.Tensor, algo="glynn", accum="dd", chunk_log2: int = 0, waves: 
         out = torch.empty((), dtype=torch.complex128, device=a.device)
     o = opts(algo, accum, chunk_log2, waves)
     check(lib().ph_perm(_ptr(a), n, lda, _ptr(out), ctypes.byref(o), _stream(a)))
+    return out
+
+
+def perm_ryser_paired(a: torch.Tensor, accum="dd", chunk_log2: int = 0,
+                      out: torch.Tensor | None = None) -> torch.Tensor:
+    """Per(a) for an n x n complex128 matrix (n <= 32, rows may be strided) by
+    Ryser's formula with the complement pairing of Algorithm S3
+    (ph_perm_ryser_paired): a 0-dim complex128 tensor."""
+    _need_c128_cuda("a", a)
+    if a.dim() != 2 or a.shape[0] != a.shape[1]:
+        raise ValueError("a must be n x n")
+    n = a.shape[0]
+    if n > 0 and a.stride(1) != 1:
+        a = a.contiguous()
+    if out is None:
+        out = torch.empty((), dtype=torch.complex128, device=a.device)
+    o = opts("ryser", accum, chunk_log2)
+    check(lib().ph_perm_ryser_paired(_ptr(a), n, a.stride(0) if n > 0 else 1, _ptr(out), ctypes.byref(o),
+                                     _stream(a)))
     return out
 
 

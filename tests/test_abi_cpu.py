@@ -70,6 +70,24 @@ def test_argument_errors_are_reported_before_any_device_work(L):
     assert _perm(L, fake, 10, 10, fake, P.PhOpts(0, 0, 0, 0, 4)) == P.PH_EINVAL  # unknown flag bit
 
 
+def test_paired_ryser_argument_errors_before_any_device_work(L):
+    from paper_1606_05836_amd import permhip as P
+
+    fake = 0x1000  # never dereferenced: validation fails first
+
+    def paired(a, n, lda, out, o=None):
+        return L.ph_perm_ryser_paired(ctypes.c_void_p(a), n, lda, ctypes.c_void_p(out),
+                                      ctypes.byref(o) if o else None, None)
+
+    assert paired(fake, -1, 1, fake) == P.PH_EINVAL
+    assert paired(fake, 33, 64, fake) == P.PH_ERANGE
+    assert b"n=33" in L.ph_last_error()
+    assert paired(fake, 10, 9, fake) == P.PH_EINVAL
+    assert paired(fake, 10, 10, 0) == P.PH_EINVAL
+    assert paired(0, 10, 10, fake) == P.PH_EINVAL
+    assert paired(fake, 10, 10, fake, P.PhOpts(1, 5, 0, 0, 0)) == P.PH_EINVAL
+
+
 def test_python_binding_rejects_non_device_tensors():
     import torch
 
