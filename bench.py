@@ -144,8 +144,8 @@ def large_share(ph, dev, stream, n):
 
 
 def extras(ph, dev, stream):
-    """Small-call latency, batched perms/s, the backward/forward ratio, the
-    largest orders' shares and the boson workload."""
+    """Small-call latency, the paired Ryser order, batched perms/s, the
+    backward/forward ratio, the largest orders' shares and the boson workload."""
     import numpy as np
     import torch
 
@@ -180,6 +180,16 @@ def extras(ph, dev, stream):
     _log("latency: " + ", ".join(f"{k} {v['device_us']:.0f} us ({v['host_us']:.0f} us host)" for k, v in lat.items()))
     res["latency"] = {"workload": "one call: 20 x 20 block of Haar(400, 11) (lda 400); 12 x 12 integers in -3..3 "
                                   "(seed 12); median of 100", **lat}
+    # Ryser's formula in the load-balanced order of Algorithm S3 against the
+    # plain Ryser sweep, n = 30 block of Haar(1600, 31)
+    a30 = torch.from_numpy(inputs.config3_matrix(30)).to(dev)
+    ph.perm_ryser_paired(a30)
+    paired = _median(_event_ms(lambda: ph.perm_ryser_paired(a30), 3, stream))
+    ph.perm(a30, algo="ryser")
+    plain_r = _median(_event_ms(lambda: ph.perm(a30, algo="ryser"), 3, stream))
+    _log(f"ryser n=30: paired (Algorithm S3 order) {paired:.2f} ms, plain {plain_r:.2f} ms")
+    res["ryser_paired"] = {"workload": "Per of the n = 30 block of Haar(1600, 31), Ryser's formula, 2^30 subsets",
+                           "paired_ms": paired, "plain_ms": plain_r, "subsets_per_s": 2.0 ** 30 / (paired / 1e3)}
     # 4096 permanents, n ~ U{16..26}, one persistent graph replay
     ns, mats = inputs.config2_batch()
     flat = torch.from_numpy(np.concatenate([m.reshape(-1) for m in mats])).to(dev)
