@@ -1,5 +1,6 @@
 // Ryser's formula with the complement pairing of Supplementary Algorithm S3
-// (gfx950), one lane per chunk of the pairing loop.
+// (gfx950): one lane, or from n = 19 a pair of lanes, per chunk of the
+// pairing loop.
 //
 // Eq. (S1) sums over all 2^n column subsets S.  Algorithm S3 runs its loop
 // over the subsets S of the first n - 1 columns only and takes with each the
@@ -15,9 +16,13 @@
 // and the fixed-order finalize of the one-matrix sweeps, which apply the
 // formula's (-1)^n.
 //
-// The row totals are read from LDS at every term (4n more VGPRs would not
-// leave room at n = 32), so this walk does the work of the plain Ryser sweep
-// plus n complex subtractions per term, with half the Gray steps.
+// Up to n = 18 one lane takes a loop index, with the row totals read from
+// LDS at every term.  From n = 19 the rows of both sums would not fit one
+// lane at two waves per SIMD, so lanes l and l + 32 share the index as in the
+// two-lane forward sweep: each holds R = ceil(n/2) rows of r_i(S) and of T_i
+// (in registers), forms its half of both products, and the upper lane's two
+// halves reach the lower lane through v_permlane32_swap.  For odd n the upper
+// lane's last row is padding with r = 1 and T = 2, so both of its factors are 1.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,10 +33,12 @@
 #include "ph_host.hpp"
 #include "ph_internal.hpp"
 #include "sweep.hpp"
+#include "sweep_pair.hpp"
 
 namespace ph {
 
 constexpr int PAIRED_NMAX = 32;
+constexpr int PAIRED_TWO_LANE_NMIN = 19;
 
 template <int N>
 __global__ __launch_bounds__(256) void k_ryser_paired(const double2* __restrict__ a, int64_t lda, int c,
@@ -107,10 +114,106 @@ __global__ __launch_bounds__(256) void k_ryser_paired(const double2* __restrict_
   if ((threadIdx.x & 63) == 0) partials[wave] = make_double4(acc.hr, acc.lr, acc.hi, acc.li);
 }
 
+template <int N>
+__global__ __launch_bounds__(256) void k_ryser_paired_2l(const double2* __restrict__ a, int64_t lda, int c,
+                                                         uint64_t nchunks, double4* __restrict__ partials,
+                                                         int plain) {
+  constexpr int R = (N + 1) / 2, RS = 2 * R;
+  extern __shared__ double2 lds_paired[];
+  double2* col = lds_paired;           // column j of A at col + j * RS, rows >= N zero
+  double2* tot = lds_paired + N * RS;  // row totals T_i; 2 on a padding row
+  for (int e = threadIdx.x; e < N * RS; e += blockDim.x) {
+    const int j = e / RS, i = e % RS;
+    col[e] = i < N ? a[(int64_t)i * lda + j] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < RS; i += blockDim.x) {
+    double2 s = make_double2(i < N ? 0.0 : 2.0, 0.0);
+    if (i < N) {
+      for (int j = 0; j < N; ++j) {
+        s.x += col[j * RS + i].x;
+        s.y += col[j * RS + i].y;
+      }
+    }
+    tot[i] = s;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const bool upper = lane >= 32;
+  const int row0 = upper ? R : 0;
+  double2 tr[R];  // this lane's row totals
+#pragma unroll
+  for (int i = 0; i < R; ++i) tr[i] = tot[row0 + i];
+  const double sgn_c = (N & 1) ? -1.0 : 1.0;
+  // lanes l and l + 32 of a wavefront form one pair and take the same chunks
+  const uint64_t pairs = (uint64_t)gridDim.x * (blockDim.x >> 1);
+  const uint64_t pid = (uint64_t)blockIdx.x * (blockDim.x >> 1) + (threadIdx.x >> 6) * 32 + (lane & 31);
+  const uint32_t len = 1u << c;
+  dd2 acc = {0.0, 0.0, 0.0, 0.0};
+  for (uint64_t ch = pid; ch < nchunks; ch += pairs) {
+    const uint64_t k0 = ch << c;
+    uint64_t g = k0 ^ (k0 >> 1);
+    double2 r[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) r[i] = make_double2(row0 + i < N ? 0.0 : 1.0, 0.0);
+#pragma unroll 1
+    for (int j = 0; j < N - 1; ++j) {
+      if ((g >> j) & 1) {
+        const double2* cj = col + j * RS + row0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          r[i].x += cj[i].x;
+          r[i].y += cj[i].y;
+        }
+      }
+    }
+    double2 sb = make_double2(0.0, 0.0), up_p = make_double2(0.0, 0.0), up_q = make_double2(0.0, 0.0);
+    for (uint32_t t = 0; t < len; ++t) {
+      if (t != 0) {
+        const int b = __builtin_ctz(t);
+        g ^= (uint64_t)1 << b;
+        const double w = ((g >> b) & 1) ? 1.0 : -1.0;
+        const double2* cb = col + b * RS + row0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          r[i].x = fma(w, cb[i].x, r[i].x);
+          r[i].y = fma(w, cb[i].y, r[i].y);
+        }
+      }
+      double2 p = r[0];
+      double2 q = make_double2(tr[0].x - r[0].x, tr[0].y - r[0].y);
+#pragma unroll
+      for (int i = 1; i < R; ++i) {
+        p = cmul(p, r[i]);
+        q = cmul(q, make_double2(tr[i].x - r[i].x, tr[i].y - r[i].y));
+      }
+      // lower lanes receive the upper half's factors (up_* held last term's)
+      from_upper(p.x, up_p.x);
+      from_upper(p.y, up_p.y);
+      from_upper(q.x, up_q.x);
+      from_upper(q.y, up_q.y);
+      const double2 pp = cmul(p, up_p), qq = cmul(q, up_q);
+      const double s = ((k0 + t) & 1) ? -1.0 : 1.0;  // (-1)^|S|
+      sb.x = fma(s, fma(sgn_c, qq.x, pp.x), sb.x);
+      sb.y = fma(s, fma(sgn_c, qq.y, pp.y), sb.y);
+      if (((t + 1) & 15) == 0 || t + 1 == len) flush(acc, sb, plain != 0, !upper);
+    }
+  }
+  acc = wave_reduce(acc, plain != 0);
+  const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (lane == 0) partials[wave] = make_double4(acc.hr, acc.lr, acc.hi, acc.li);
+}
+
+template <int N>
+static const void* paired_kernel() {
+  if constexpr (N < PAIRED_TWO_LANE_NMIN) return (const void*)&k_ryser_paired<N>;
+  else return (const void*)&k_ryser_paired_2l<N>;
+}
+
 template <int... Is>
 static const void* paired_lookup(int n, std::integer_sequence<int, Is...>) {
   const void* out = nullptr;
-  ((n == Is + 1 ? (out = (const void*)&k_ryser_paired<Is + 1>, 0) : 0), ...);
+  ((n == Is + 1 ? (out = paired_kernel<Is + 1>(), 0) : 0), ...);
   return out;
 }
 
@@ -131,13 +234,17 @@ static int perm_ryser_paired(const double2* A, int n, int64_t lda, double2* out,
   int c = o.chunk_log2 > 0 ? o.chunk_log2 : std::min(10, nb - 17);
   c = std::max(0, std::min(c, nb));
   const uint64_t nchunks = (uint64_t)1 << (nb - c);
-  const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>((nchunks + 255) / 256, (uint64_t)cus * 2));
+  const bool two_lane = n >= PAIRED_TWO_LANE_NMIN;
+  const uint64_t per_block = two_lane ? 128 : 256;  // chunks a workgroup takes at a time
+  const uint64_t blocks =
+      std::max<uint64_t>(1, std::min<uint64_t>((nchunks + per_block - 1) / per_block, (uint64_t)cus * 2));
   const uint64_t nwaves = blocks * 4;
   void* ws = nullptr;
   int rc = workspace(st, nwaves * sizeof(double4), &ws);
   if (rc) return rc;
   double4* pw = static_cast<double4*>(ws);
-  const size_t lds = (size_t)(n * n + n) * sizeof(double2);
+  const int rs = two_lane ? 2 * ((n + 1) / 2) : n;  // rows per stored column
+  const size_t lds = (size_t)(n * rs + rs) * sizeof(double2);
   const double2* a = A;
   int64_t ld = lda;
   uint64_t nch = nchunks;
