@@ -117,6 +117,8 @@ def test_two_permutations_closed_form_bit_exact(ph, n):
     # and a diagonal D of units: every row sum and complement sum has modulus
     # <= 2, so every term is an exact integer and the sum is exact.  Covers the
     # one-lane walk (n <= 18) and the two-lane walk, odd n with its padding row.
+    # The closed form is pinned against the definition on the CPU
+    # (test_two_permutations_closed_form in tests/test_oracle_pins.py).
     rng = np.random.default_rng(4000 + n)
     p, q = rng.permutation(n), rng.permutation(n)
     a = np.zeros((n, n), np.complex128)

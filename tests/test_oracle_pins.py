@@ -266,6 +266,31 @@ def test_ryser_paired_algorithm_s3(n):
     assert O.ryser_paired_int(g) == O.perm_brute_int(g)
 
 
+@pytest.mark.parametrize("n", range(1, 8))
+def test_two_permutations_closed_form(n):
+    # Per(D (P + Q)) = prod(D) 2^(cycles of P^-1 Q) for permutation matrices
+    # P, Q and a diagonal D of units (the GPU tests use it at n up to 40):
+    # Per(P + Q) = Per(I + P^-1 Q), and each cycle of P^-1 Q is a block whose
+    # permanent is 2 (the identity and the cycle; a fixed point's entry is 2)
+    for seed in range(4):
+        rng = np.random.default_rng(100 * n + seed)
+        p, q = rng.permutation(n), rng.permutation(n)
+        a = np.zeros((n, n), np.complex128)
+        a[np.arange(n), p] += 1
+        a[np.arange(n), q] += 1
+        units = np.array([1, 1j, -1, -1j])[rng.integers(0, 4, n)]
+        sigma = np.argsort(p)[q]
+        seen, cyc = set(), 0
+        for i in range(n):
+            if i not in seen:
+                cyc += 1
+                while i not in seen:
+                    seen.add(i)
+                    i = sigma[i]
+        want = complex(np.prod(units)) * 2.0 ** cyc
+        assert O.to_complex(O.perm_exact(units[:, None] * a, "brute")) == want
+
+
 # ------------------------------------------------------ values the paper prints
 
 def _printed_match(value: float, printed: str) -> bool:
