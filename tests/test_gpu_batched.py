@@ -7,6 +7,7 @@ import pytest
 
 import inputs as I
 import oracle as O
+from tests import _closed_forms as CF
 from tests import _golden as G
 
 torch = pytest.importorskip("torch")
@@ -155,3 +156,15 @@ def test_batch_with_a_large_order_takes_the_two_lane_sweep(ph):
     assert complex(got[0]) == complex(-4194304, -4194304)
     assert complex(got[1]) == O.to_complex(O.perm_exact(mats[1]))
     assert O.rel_err(complex(got[2]), O.perm_exact(mats[2])) <= 1e-12
+
+
+def test_two_permutations_closed_form_every_bucket(ph):
+    # D (P + Q) across the size buckets of the batched kernels (1..16, 17..24,
+    # 25..32, 33..40): exact permanents at sizes no exact oracle value reaches
+    ns = [5, 16, 17, 24, 25, 32, 33, 36, 37, 40]
+    mats, wants = zip(*[CF.two_permutations(n, 6000 + n) for n in ns])
+    got = ph.perm_batched([torch.from_numpy(m).to("cuda") for m in mats]).cpu().numpy()
+    assert [complex(x) for x in got] == list(wants)
+    small = [i for i, n in enumerate(ns) if n <= 36]
+    got_r = ph.perm_batched([torch.from_numpy(mats[i]).to("cuda") for i in small], algo="ryser").cpu().numpy()
+    assert [complex(x) for x in got_r] == [wants[i] for i in small]

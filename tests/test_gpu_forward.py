@@ -15,6 +15,7 @@ import pytest
 
 import inputs as I
 import oracle as O
+from tests import _closed_forms as CF
 from tests import _golden as G
 
 torch = pytest.importorskip("torch")
@@ -259,33 +260,10 @@ def test_full_size_pins(ph, n):
     assert abs(run(ph, a, accum="plain") - g) <= 1e-8 * abs(g)
 
 
-def _two_permutations(n, seed):
-    """D (P + Q) for permutation matrices P, Q and a diagonal D of units, and its
-    permanent prod(D) 2^(cycles of P^-1 Q): every row sum of either formula
-    has modulus <= 2, so every term is an exact integer and the sum is exact.
-    The closed form is pinned against the definition on the CPU
-    (test_two_permutations_closed_form in tests/test_oracle_pins.py)."""
-    rng = np.random.default_rng(seed)
-    p, q = rng.permutation(n), rng.permutation(n)
-    a = np.zeros((n, n), np.complex128)
-    a[np.arange(n), p] += 1
-    a[np.arange(n), q] += 1
-    units = np.array([1, 1j, -1, -1j])[rng.integers(0, 4, n)]
-    sigma = np.argsort(p)[q]
-    seen, cyc = set(), 0
-    for i in range(n):
-        if i not in seen:
-            cyc += 1
-            while i not in seen:
-                seen.add(i)
-                i = sigma[i]
-    return units[:, None] * a, complex(np.prod(units)) * 2.0 ** cyc
-
-
 @pytest.mark.parametrize("n,algos", [(33, ("glynn", "ryser")), (36, ("glynn", "ryser")), (40, ("glynn",))])
 def test_two_permutations_closed_form_at_large_n(ph, n, algos):
     # exact full sums at the sizes where no Haar value is computable, the
     # benchmark's n = 40 launch shape included
-    a, want = _two_permutations(n, 5000 + n)
+    a, want = CF.two_permutations(n, 5000 + n)
     for algo in algos:
         assert run(ph, a, algo=algo) == want, algo

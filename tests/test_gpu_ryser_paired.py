@@ -13,6 +13,7 @@ import pytest
 
 import inputs as I
 import oracle as O
+from tests import _closed_forms as CF
 from tests import _golden as G
 
 torch = pytest.importorskip("torch")
@@ -100,17 +101,6 @@ def test_orders_beyond_the_kernels_raise(ph):
         ph.perm_ryser_paired(cuda(np.ones((33, 33), np.complex128)))
 
 
-def cycles(perm):
-    seen, count = set(), 0
-    for i in range(len(perm)):
-        if i not in seen:
-            count += 1
-            while i not in seen:
-                seen.add(i)
-                i = perm[i]
-    return count
-
-
 @pytest.mark.parametrize("n", [13, 17, 18, 19, 20, 23, 26, 31, 32])
 def test_two_permutations_closed_form_bit_exact(ph, n):
     # Per(D (P + Q)) = prod(D) 2^(cycles of P^-1 Q) for permutation matrices P, Q
@@ -119,14 +109,6 @@ def test_two_permutations_closed_form_bit_exact(ph, n):
     # one-lane walk (n <= 18) and the two-lane walk, odd n with its padding row.
     # The closed form is pinned against the definition on the CPU
     # (test_two_permutations_closed_form in tests/test_oracle_pins.py).
-    rng = np.random.default_rng(4000 + n)
-    p, q = rng.permutation(n), rng.permutation(n)
-    a = np.zeros((n, n), np.complex128)
-    a[np.arange(n), p] += 1
-    a[np.arange(n), q] += 1
-    units = np.array([1, 1j, -1, -1j])[rng.integers(0, 4, n)]
-    a = units[:, None] * a
-    inv_p = np.argsort(p)
-    want = complex(np.prod(units)) * 2.0 ** cycles([inv_p[q[i]] for i in range(n)])
+    a, want = CF.two_permutations(n, 4000 + n)
     assert complex(ph.perm_ryser_paired(cuda(a)).cpu()) == want
     assert complex(ph.perm(cuda(a)).cpu()) == want  # BB/FG on the same matrix

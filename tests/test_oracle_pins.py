@@ -15,6 +15,7 @@ import pytest
 import inputs as I
 import oracle as O
 from oracle import exact as OX
+from tests import _closed_forms as CF
 
 GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
 
@@ -273,22 +274,8 @@ def test_two_permutations_closed_form(n):
     # Per(P + Q) = Per(I + P^-1 Q), and each cycle of P^-1 Q is a block whose
     # permanent is 2 (the identity and the cycle; a fixed point's entry is 2)
     for seed in range(4):
-        rng = np.random.default_rng(100 * n + seed)
-        p, q = rng.permutation(n), rng.permutation(n)
-        a = np.zeros((n, n), np.complex128)
-        a[np.arange(n), p] += 1
-        a[np.arange(n), q] += 1
-        units = np.array([1, 1j, -1, -1j])[rng.integers(0, 4, n)]
-        sigma = np.argsort(p)[q]
-        seen, cyc = set(), 0
-        for i in range(n):
-            if i not in seen:
-                cyc += 1
-                while i not in seen:
-                    seen.add(i)
-                    i = sigma[i]
-        want = complex(np.prod(units)) * 2.0 ** cyc
-        assert O.to_complex(O.perm_exact(units[:, None] * a, "brute")) == want
+        a, want = CF.two_permutations(n, 100 * n + seed)
+        assert O.to_complex(O.perm_exact(a, "brute")) == want
 
 
 # ------------------------------------------------------ values the paper prints
