@@ -7,6 +7,7 @@ import pytest
 
 import inputs as I
 import oracle as O
+from tests import _closed_forms as CF
 from tests import _golden as G
 
 torch = pytest.importorskip("torch")
@@ -175,3 +176,19 @@ def test_sweep_permanent_against_stored_exact(ph, n):
         pytest.skip("stored value absent")
     p, _ = ph.perm_grad(cuda(a))
     assert O.rel_err(complex(p.cpu()), ex) <= 1e-10
+
+
+@pytest.mark.parametrize("n", [5, 12, 17, 20, 21, 24, 25, 32])
+def test_two_permutations_exact_minors(ph, n):
+    # D (P + Q) (tests/_closed_forms.py): every row sum of the sweep has modulus
+    # <= 2, so every leave-one-out product and running sum is an exact integer
+    # and the minors come out exactly.  One case per lane layout (4 x 2, 8 x 2,
+    # 4 x 5, 8 x 3, 8 x 4 rows); the Laplace expansions along every row and
+    # every column (two nonzero entries each) give Per bit for bit.
+    a, want = CF.two_permutations(n, 7000 + n)
+    p, g = ph.perm_grad(cuda(a))
+    assert complex(p.cpu()) == want
+    m = np.conj(g.cpu().numpy())
+    assert np.array_equal(m.real, np.round(m.real)) and np.array_equal(m.imag, np.round(m.imag))
+    assert np.all((a * m).sum(axis=1) == want)
+    assert np.all((a * m).sum(axis=0) == want)
