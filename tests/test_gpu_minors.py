@@ -6,6 +6,7 @@ import pytest
 
 import inputs as I
 import oracle as O
+from tests import _closed_forms as CF
 from oracle import sampler as OS
 
 torch = pytest.importorskip("torch")
@@ -96,3 +97,16 @@ def test_plain_accumulation_and_batch_shapes(ph):
         assert (dd - pl).abs().max().item() <= 1e-12 * big
     with pytest.raises(ValueError):
         ph.perm_row_minors(torch.zeros((3, 3), dtype=torch.complex128, device="cuda"))
+
+
+@pytest.mark.parametrize("n", [5, 11, 12, 16, 20, 25, 29, 31])
+def test_two_permutations_row_expansion_exact(ph, n):
+    # C = D (P + Q), (n + 1) x (n + 1) (tests/_closed_forms.py), and B its
+    # first n rows: every row sum of the sweep has modulus <= 2, so the n + 1
+    # minors of B are exact Gaussian integers and the expansion along C's last
+    # row is Per(C) bit for bit (the gradient path below 12 rows, the row sweep
+    # from 12)
+    c, want = CF.two_permutations(n + 1, 8000 + n)
+    minors = ph.perm_row_minors(torch.from_numpy(np.ascontiguousarray(c[:n])).to("cuda")).cpu().numpy()
+    assert np.array_equal(minors.real, np.round(minors.real)) and np.array_equal(minors.imag, np.round(minors.imag))
+    assert complex((c[n] * minors).sum()) == want
