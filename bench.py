@@ -129,7 +129,7 @@ def large_share(ph, dev, stream, n):
 
     import inputs
 
-    an = torch.from_numpy(inputs.config3_matrix(n)).to(dev)
+    an = torch.from_numpy(inputs.haar1600_block(n)).to(dev)
     total = 1 << (n - 1)
     kb, m = 3 * (total // 8), 1 << 37
     ph.perm_partial(an, kb, kb + (1 << 24))
@@ -158,7 +158,7 @@ def extras(ph, dev, stream):
     # stream synchronised)
     u1 = torch.from_numpy(inputs.haar(400, 11)).to(dev)
     a1 = u1[:20, :20]
-    b1 = torch.from_numpy(inputs.config1_int12()).to(dev)
+    b1 = torch.from_numpy(inputs.int12_matrix()).to(dev)
     lat = {}
     for name, m, algo, accum in (("haar20_glynn_dd", a1, "glynn", "dd"), ("haar20_glynn_plain", a1, "glynn", "plain"),
                                  ("haar20_ryser_dd", a1, "ryser", "dd"), ("int12_glynn_dd", b1, "glynn", "dd")):
@@ -182,7 +182,7 @@ def extras(ph, dev, stream):
                                   "(seed 12); median of 100", **lat}
     # Ryser's formula in the load-balanced order of Algorithm S3 against the
     # plain Ryser sweep, n = 30 block of Haar(1600, 31)
-    a30 = torch.from_numpy(inputs.config3_matrix(30)).to(dev)
+    a30 = torch.from_numpy(inputs.haar1600_block(30)).to(dev)
     ph.perm_ryser_paired(a30)
     paired = _median(_event_ms(lambda: ph.perm_ryser_paired(a30), 3, stream))
     ph.perm(a30, algo="ryser")
@@ -191,7 +191,7 @@ def extras(ph, dev, stream):
     res["ryser_paired"] = {"workload": "Per of the n = 30 block of Haar(1600, 31), Ryser's formula, 2^30 subsets",
                            "paired_ms": paired, "plain_ms": plain_r, "subsets_per_s": 2.0 ** 30 / (paired / 1e3)}
     # 4096 permanents, n ~ U{16..26}, one persistent graph replay
-    ns, mats = inputs.config2_batch()
+    ns, mats = inputs.mixed_batch_16_26()
     flat = torch.from_numpy(np.concatenate([m.reshape(-1) for m in mats])).to(dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -210,7 +210,7 @@ def extras(ph, dev, stream):
     }
     plan.close()
     # backward of L = |perm|^2 against the forward, 1024 matrices of n = 20
-    a4 = torch.from_numpy(inputs.config4_batch()).to(dev)
+    a4 = torch.from_numpy(inputs.grad_batch_20()).to(dev)
     p4 = ph.perm_batched(a4)
     g4 = 2 * p4
     fwd = _median(_event_ms(lambda: ph.perm_batched(a4), 7, stream))
@@ -224,7 +224,7 @@ def extras(ph, dev, stream):
     # the full-sum time it implies on 1 and on 8 devices (a projection)
     res["large_share"] = {str(n): large_share(ph, dev, stream, n) for n in (48, 50)}
     # boson sampling: Eq. (1) probabilities and their gradient
-    u, ins, pats = inputs.config5_workload()
+    u, ins, pats = inputs.boson_workload()
     ud = torch.from_numpy(u).to(dev)
     ph.boson_probs(ud, ins, pats)
     pf = _median(_event_ms(lambda: ph.boson_probs(ud, ins, pats), 3, stream))
@@ -255,7 +255,7 @@ def grad_ratio(ph, dev, stream, ns):
     res = {}
     for n in ns:
         batch = max(8, 1 << max(0, 30 - n))
-        a = torch.from_numpy(inputs.config4_batch(batch, n)).to(dev)
+        a = torch.from_numpy(inputs.grad_batch_20(batch, n)).to(dev)
         reps = 2 if n >= 30 else 3
         ph.perm_batched(a)
         fwd = _median(_event_ms(lambda: ph.perm_batched(a), reps, stream))
@@ -305,7 +305,7 @@ def precision(ph, dev, large):
 
     rows = []
     for name, (n, sha, exact) in sorted(_stored_exact().items(), key=lambda kv: kv[1][0]):
-        a = inputs.config1_haar20() if name == "config1_haar20" else inputs.config3_matrix(n)
+        a = inputs.haar400_block20() if name == "haar400_block20" else inputs.haar1600_block(n)
         if inputs.sha256_of(a) != sha:
             raise RuntimeError(f"{name}: input bytes differ from the stored ones")
         row = {"name": name, "n": n}
@@ -317,7 +317,7 @@ def precision(ph, dev, large):
         _log(f"precision: {name} done")
     big = []
     for n in large:
-        a = inputs.config3_matrix(n)
+        a = inputs.haar1600_block(n)
         gd, t_gd = run(a, "glynn", "dd")
         _log(f"precision: n={n} glynn dd {t_gd / 1e3:.1f} s")
         gp, t_gp = run(a, "glynn", "plain")
@@ -444,7 +444,7 @@ def main():
     import paper_1606_05836_amd as ph
 
     n = args.n
-    a_host = inputs.config3_matrix(n)
+    a_host = inputs.haar1600_block(n)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     a = torch.from_numpy(a_host).to(dev)

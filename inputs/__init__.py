@@ -13,11 +13,11 @@ from .gen import (  # noqa: F401
     diag_matrix,
     submatrix,
     sha256_of,
-    config1_haar20,
-    config1_int12,
-    config2_batch,
-    config3_matrix,
-    config4_batch,
-    config5_workload,
+    haar400_block20,
+    int12_matrix,
+    mixed_batch_16_26,
+    haar1600_block,
+    grad_batch_20,
+    boson_workload,
     collision_pattern,
 )

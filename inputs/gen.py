@@ -71,17 +71,17 @@ def sha256_of(a: np.ndarray) -> str:
 
 # ---------------------------------------------------------------- workloads
 
-def config1_haar20() -> np.ndarray:
+def haar400_block20() -> np.ndarray:
     """Top-left 20 x 20 block of Haar(400, seed 11)."""
     return submatrix(haar(400, 11), range(20), range(20))
 
 
-def config1_int12() -> np.ndarray:
+def int12_matrix() -> np.ndarray:
     """12 x 12 integer matrix, entries uniform in {-3..3}, seed 12."""
     return int_matrix(12, -3, 3, 12)
 
 
-def config2_batch(batch: int = 4096, seed_ns: int = 21, seed_rows: int = 22):
+def mixed_batch_16_26(batch: int = 4096, seed_ns: int = 21, seed_rows: int = 22):
     """Batch of n x n submatrices with n ~ U{16..26}.
 
     For each n the parent is Haar(n^2, 2000+n); matrix b takes n distinct random
@@ -98,14 +98,14 @@ def config2_batch(batch: int = 4096, seed_ns: int = 21, seed_rows: int = 22):
     return ns.astype(np.int32), mats
 
 
-def config3_matrix(n: int) -> np.ndarray:
+def haar1600_block(n: int) -> np.ndarray:
     """n x n submatrix of Haar(1600, 31): sorted random rows (seed 32+n), first n columns."""
     u = haar(1600, 31)
     rows = np.sort(np.random.default_rng(32 + n).choice(1600, n, replace=False))
     return submatrix(u, rows, range(n))
 
 
-def config4_batch(batch: int = 1024, n: int = 20):
+def grad_batch_20(batch: int = 1024, n: int = 20):
     """batch x n x n submatrices of Haar(400, 41), rows drawn with seed 42."""
     u = haar(400, 41)
     rng = np.random.default_rng(42)
@@ -132,7 +132,7 @@ def collision_pattern(rng: np.random.Generator, m: int, n: int) -> np.ndarray:
     return np.sort(np.asarray(out, dtype=np.int64))
 
 
-def config5_workload(m: int = 900, n: int = 30, patterns: int = 256, seed_u: int = 51, seed_p: int = 52):
+def boson_workload(m: int = 900, n: int = 30, patterns: int = 256, seed_u: int = 51, seed_p: int = 52):
     """Boson-sampling workload: U = Haar(m, 51), inputs in modes 0..n-1 (one photon
     each), ``patterns`` collision output patterns drawn with seed 52.
 

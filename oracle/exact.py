@@ -401,7 +401,7 @@ def certify_int_exact(a, ryser: bool = False) -> dict:
       * every partial sum of terms, in any order: sum over terms of
         |term|_1 < 2^53.
     The walk is Eq. (S2) in Gray order (or Eq. (S1) over all subsets when
-    ``ryser``).  Returns the two bounds and the verdict.
+    ``ryser``).  Returns the two bounds and whether both hold.
     """
     g, d = to_gaussian_integers(a)
     if d != 1:

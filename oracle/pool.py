@@ -1,4 +1,4 @@
-"""Multi-process driver for the exact Glynn oracle.
+"""Multi-process runner for the exact Glynn oracle.
 
 TEST INFRASTRUCTURE ONLY (tests/, __graft_entry__.smoke(), bench.py's
 cpu_baseline leg).

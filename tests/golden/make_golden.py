@@ -61,24 +61,24 @@ def _run(path, jobs, workers):
 
 
 def haar_jobs():
-    yield "config1_haar20", I.config1_haar20()
+    yield "haar400_block20", I.haar400_block20()
     for n in (22, 24, 26, 28, 30):
-        yield f"config3_n{n}", I.config3_matrix(n)
+        yield f"haar1600_block_n{n}", I.haar1600_block(n)
 
 
 def batch_jobs():
-    ns, mats = I.config2_batch()
+    ns, mats = I.mixed_batch_16_26()
     picks = set(int(x) for x in np.random.default_rng(23).choice(len(ns), 32, replace=False))
     picks |= {b for b, n in enumerate(ns) if n <= 17}
     for b in sorted(picks, key=lambda b: (ns[b], b)):
-        yield f"config2_b{b}", mats[b]
+        yield f"mixed_batch_b{b}", mats[b]
 
 
 def minors_jobs():
-    a = I.config4_batch()[0]
+    a = I.grad_batch_20()[0]
     for i in range(a.shape[0]):
         for j in range(a.shape[1]):
-            yield f"config4_m0_{i}_{j}", O.minor(a, i, j)
+            yield f"grad_batch_m0_{i}_{j}", O.minor(a, i, j)
 
 
 def main():

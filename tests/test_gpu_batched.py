@@ -84,11 +84,11 @@ def test_plan_replay_with_new_pointers_and_offsets(ph):
     assert np.array_equal(r3, r1)
 
 
-def test_config2_batch_against_stored_exact(ph):
+def test_mixed_batch_against_stored_exact(ph):
     """The 4096-matrix benchmark batch (n ~ U{16..26}) in one plan; every
     matrix with a stored exact value (all n <= 17 and 32 sampled ones) must
     be within 1e-10."""
-    ns, mats = I.config2_batch()
+    ns, mats = I.mixed_batch_16_26()
     gold = G.load("batch")
     if not gold:
         pytest.skip("no stored batch values")
@@ -96,7 +96,7 @@ def test_config2_batch_against_stored_exact(ph):
     got = plan(packed(mats)).cpu().numpy()
     checked = 0
     for name, (n, sha, v) in gold.items():
-        b = int(name.split("_b")[1])
+        b = int(name.rsplit("_b", 1)[1])
         assert I.sha256_of(mats[b]) == sha and ns[b] == n
         assert O.rel_err(complex(got[b]), v) <= 1e-10, (b, n)
         checked += 1
@@ -116,7 +116,7 @@ def test_fp64_peak_microbenchmark(ph):
 def test_perm_of_leading_batch_dims(ph):
     # perm(a) with a (..., n, n) tensor goes through the batched path; the
     # values match the oracle matrix by matrix
-    a = I.config4_batch(6, 9).reshape(2, 3, 9, 9)
+    a = I.grad_batch_20(6, 9).reshape(2, 3, 9, 9)
     got = ph.perm(torch.from_numpy(a).to("cuda"))
     assert got.shape == (2, 3)
     for i in range(2):
@@ -151,7 +151,7 @@ def test_larger_size_buckets_exact(ph):
 def test_batch_with_a_large_order_takes_the_two_lane_sweep(ph):
     # orders >= 45 in a batch are swept one by one after the plan's graph (two
     # lanes per term); the small ones stay in the graph
-    mats = [I.diag_matrix(45, 1 + 1j), gauss_int(6, 1), I.config3_matrix(20)]
+    mats = [I.diag_matrix(45, 1 + 1j), gauss_int(6, 1), I.haar1600_block(20)]
     got = ph.perm_batched([torch.from_numpy(m).to("cuda") for m in mats]).cpu().numpy()
     assert complex(got[0]) == complex(-4194304, -4194304)
     assert complex(got[1]) == O.to_complex(O.perm_exact(mats[1]))

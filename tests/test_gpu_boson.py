@@ -93,7 +93,7 @@ def test_grouped_sweeps_against_multiplicity_route(ph):
 
 def test_reduced_workload_against_oracle(ph):
     # the full workload's recipe (Haar(900), collision patterns) at 16 photons
-    u, ins, pats = I.config5_workload(n=16, patterns=8)
+    u, ins, pats = I.boson_workload(n=16, patterns=8)
     pr = ph.boson_probs(cuda(u), ins, pats).cpu().numpy()
     for k in range(len(pats)):
         e = float(O.prob_exact(u, ins, pats[k]))
@@ -207,7 +207,7 @@ def test_autograd_gradcheck(ph):
 
 @pytest.fixture(scope="module")
 def full_workload(ph):
-    u, ins, pats = I.config5_workload()
+    u, ins, pats = I.boson_workload()
     ud = cuda(u)
     w = np.random.default_rng(53).uniform(0.5, 1.5, len(pats))
     pf = ph.boson_probs(ud, ins, pats)

@@ -61,8 +61,8 @@ def c_exact(v):
 
 @pytest.mark.parametrize("algo", ["glynn", "ryser"])
 @pytest.mark.parametrize("accum", ["dd", "plain"])
-def test_config1_integer_12x12_bit_exact(ph, algo, accum):
-    b = I.config1_int12()
+def test_int12_matrix_bit_exact(ph, algo, accum):
+    b = I.int12_matrix()
     assert O.certify_int_exact(b, ryser=(algo == "ryser"))["certified"]
     assert run(ph, b, algo=algo, accum=accum) == c_exact(O.perm_exact(b))
 
@@ -103,9 +103,9 @@ def test_haar_submatrices_small_n(ph, algo):
 
 @pytest.mark.parametrize("algo", ["glynn", "ryser"])
 @pytest.mark.parametrize("accum", ["dd", "plain"])
-def test_config1_haar20(ph, algo, accum):
-    a = I.config1_haar20()
-    ex = G.value_for("haar", "config1_haar20", a) or O.perm_exact_parallel(a)
+def test_haar400_block20(ph, algo, accum):
+    a = I.haar400_block20()
+    ex = G.value_for("haar", "haar400_block20", a) or O.perm_exact_parallel(a)
     # the binding passes the 400-column parent's stride when given a view
     u = torch.from_numpy(np.array(I.haar(400, 11))).to("cuda")
     got = complex(ph.perm(u[:20, :20], algo=algo, accum=accum).cpu())
@@ -116,16 +116,16 @@ def test_config1_haar20(ph, algo, accum):
 def test_chunk_length_does_not_change_the_answer(ph, c):
     """Any chunk length gives the permanent; longer chunks accumulate more
     row-sum drift between re-seeds (c = 19 is one chunk of 2^19 steps)."""
-    a = I.config1_haar20()
-    ex = G.value_for("haar", "config1_haar20", a) or O.perm_exact_parallel(a)
+    a = I.haar400_block20()
+    ex = G.value_for("haar", "haar400_block20", a) or O.perm_exact_parallel(a)
     for waves in (0, 1):
         assert O.rel_err(run(ph, a, chunk_log2=c, waves=waves), ex) <= (1e-12 if c <= 12 else 1e-11)
 
 
 @pytest.mark.parametrize("n", [22, 24, 26, 28, 30])
 def test_haar_large_against_stored_exact(ph, n):
-    a = I.config3_matrix(n)
-    ex = G.value_for("haar", f"config3_n{n}", a)
+    a = I.haar1600_block(n)
+    ex = G.value_for("haar", f"haar1600_block_n{n}", a)
     if ex is None:
         pytest.skip(f"no stored exact value for n={n}")
     assert O.rel_err(run(ph, a), ex) <= TOL
@@ -220,7 +220,7 @@ def test_block_diagonal_scrambled(ph):
 # ---------------------------------------------------------------- properties
 
 def test_row_scaling_by_two_is_exact(ph):
-    a = I.config3_matrix(24)
+    a = I.haar1600_block(24)
     b = a.copy()
     b[5] *= 2.0
     for algo in ("glynn", "ryser"):
@@ -228,13 +228,13 @@ def test_row_scaling_by_two_is_exact(ph):
 
 
 def test_bitwise_deterministic(ph):
-    a = I.config3_matrix(26)
+    a = I.haar1600_block(26)
     x = [run(ph, a) for _ in range(3)]
     assert x[0] == x[1] == x[2]
 
 
 def test_glynn_ryser_transpose_agree(ph):
-    a = I.config3_matrix(25)
+    a = I.haar1600_block(25)
     g = run(ph, a)
     assert abs(run(ph, a, algo="ryser") - g) <= ryser_tol(25) * abs(g)
     assert abs(run(ph, a.T.copy()) - g) <= 1e-11 * abs(g)
@@ -252,7 +252,7 @@ def test_full_size_pins(ph, n):
     # all-ones: n!
     assert abs(run(ph, np.ones((n, n), np.complex128)) - math.factorial(n)) <= TOL * math.factorial(n)
     # row scaling: exact factor 2 on the Haar workload matrix, dd vs plain agree
-    a = I.config3_matrix(n)
+    a = I.haar1600_block(n)
     g = run(ph, a)
     b = a.copy()
     b[0] *= 2.0

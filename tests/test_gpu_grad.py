@@ -58,7 +58,7 @@ def test_integer_matrix_minors(ph, n):
 
 
 def test_batch_matches_single_and_upstream_scaling(ph):
-    a = I.config4_batch(6)
+    a = I.grad_batch_20(6)
     p, g = ph.perm_grad(cuda(a))
     w = torch.tensor([1 + 2j, -0.5, 3j, 1, 2, -1 - 1j], dtype=torch.complex128, device="cuda")
     p2, g2 = ph.perm_grad(cuda(a), grad_out=w)
@@ -70,10 +70,10 @@ def test_batch_matches_single_and_upstream_scaling(ph):
         assert abs(complex(pb.cpu()) - fwd) <= 1e-12 * abs(fwd)
 
 
-def test_laplace_and_euler_identities_config4(ph):
+def test_laplace_and_euler_identities_grad_batch(ph):
     """sum_j a_ij M_ij = Per(A) for every row i, sum_ij a_ij M_ij = n Per(A),
     on the 1024 x (20 x 20) benchmark batch."""
-    a = I.config4_batch()
+    a = I.grad_batch_20()
     p, g = ph.perm_grad(cuda(a))
     m = torch.conj(g)
     at = cuda(a)
@@ -88,7 +88,7 @@ def test_laplace_and_euler_identities_config4(ph):
 def test_finite_differences_n20(ph):
     """Central differences (h = 1e-6) of L = |Per(A)|^2 on the real and
     imaginary part of sampled entries, against dL/dA = 2 Per conj(M)."""
-    a = I.config4_batch(1)[0]
+    a = I.grad_batch_20(1)[0]
     p, g = ph.perm_grad(cuda(a))
     p = complex(p.cpu())
     # g = conj(M) (upstream gradient 1); PyTorch's convention for L = |p|^2:
@@ -111,12 +111,12 @@ def test_finite_differences_n20(ph):
         assert abs(num - got) <= 1e-5 * abs(got), (i, j, num, got)
 
 
-def test_sampled_minors_of_config4_matrix0(ph):
-    a = I.config4_batch(1)[0]
+def test_sampled_minors_of_grad_batch_matrix0(ph):
+    a = I.grad_batch_20(1)[0]
     _, g = ph.perm_grad(cuda(a))
     m = np.conj(g.cpu().numpy())
     gold = G.load("minors")
-    names = [k for k in gold if k.startswith("config4_m0_")]
+    names = [k for k in gold if k.startswith("grad_batch_m0_")]
     if not names:
         for i, j in [(0, 0), (19, 7)]:
             ex = O.perm_exact_parallel(O.minor(a, i, j))
@@ -133,7 +133,7 @@ def test_autograd_function(ph):
     n = 5
     a = cuda(I.submatrix(I.haar(30, 2), range(n), range(n))).requires_grad_(True)
     assert torch.autograd.gradcheck(ph.permanent, (a,), eps=1e-6, atol=1e-8, rtol=1e-6)
-    b = cuda(I.config4_batch(3)).requires_grad_(True)
+    b = cuda(I.grad_batch_20(3)).requires_grad_(True)
     loss = (ph.permanent(b).abs() ** 2).sum()
     loss.backward()
     p, g = ph.perm_grad(b.detach())
@@ -142,7 +142,7 @@ def test_autograd_function(ph):
 
 @pytest.mark.parametrize("n", [21, 25, 30, 32])
 def test_larger_n_identities(ph, n):
-    a = I.config3_matrix(n) if n <= 30 else I.submatrix(I.haar(1600, 31), range(n), range(n))
+    a = I.haar1600_block(n) if n <= 30 else I.submatrix(I.haar(1600, 31), range(n), range(n))
     p, g = ph.perm_grad(cuda(a))
     m = torch.conj(g)
     rows = (cuda(a) * m).sum(dim=1)
@@ -170,8 +170,8 @@ def test_sampled_minors_at_layout_boundaries(ph, n):
 def test_sweep_permanent_against_stored_exact(ph, n):
     # the permanent the gradient sweep produces on the way (3 and 4 rows per
     # lane) against the oracle's stored exact value
-    a = I.config3_matrix(n)
-    ex = G.value_for("haar", f"config3_n{n}", a)
+    a = I.haar1600_block(n)
+    ex = G.value_for("haar", f"haar1600_block_n{n}", a)
     if ex is None:
         pytest.skip("stored value absent")
     p, _ = ph.perm_grad(cuda(a))

@@ -99,7 +99,7 @@ def test_haar_shares_against_oracle(ph, algo):
 
 def test_one_share_is_the_whole_permanent(ph):
     for n, accum in ((20, "dd"), (20, "plain"), (27, "dd")):
-        a = cuda(I.config3_matrix(n))
+        a = cuda(I.haar1600_block(n))
         whole = complex(ph.perm(a, accum=accum).cpu())
         p = ph.perm_partial(a, 0, ph.gray_terms(n), accum=accum)
         if accum == "plain":
@@ -114,7 +114,7 @@ def test_one_share_is_the_whole_permanent(ph):
 
 
 def test_misaligned_and_out_of_range_shares_raise(ph):
-    a = cuda(I.config3_matrix(20))
+    a = cuda(I.haar1600_block(20))
     L = 1 << ph.perm_chunk_log2(20)
     with pytest.raises(ph.PermhipError):
         ph.perm_partial(a, 1, L)
@@ -127,7 +127,7 @@ def test_misaligned_and_out_of_range_shares_raise(ph):
 def test_eight_shares_of_n40_as_eight_devices(ph):
     # the contiguous split the sharded design gives 8 devices, each share at its real shape
     n = 40
-    a = cuda(I.config3_matrix(n))
+    a = cuda(I.haar1600_block(n))
     total = ph.gray_terms(n)
     parts = torch.stack([ph.perm_partial(a, total * g // 8, total * (g + 1) // 8) for g in range(8)])
     per = complex(ph.perm_combine(parts, n).cpu())
@@ -150,7 +150,7 @@ def test_large_n_share_exact_on_diag_one_plus_i(ph, n):
 
 def test_split_additivity_at_n46(ph):
     n = 46
-    a = cuda(I.config3_matrix(n))
+    a = cuda(I.haar1600_block(n))
     kb = 3 << 40
     h = 1 << 35
     p12 = ph.perm_partial(a, kb, kb + 2 * h).cpu().tolist()
@@ -166,7 +166,7 @@ def test_segmented_run_resumes_to_the_same_bits(ph, tmp_path):
     from paper_1606_05836_amd.segments import segmented_perm
 
     n = 24
-    a = cuda(I.config3_matrix(n))
+    a = cuda(I.haar1600_block(n))
     ref = segmented_perm(a, segment_log2=20)  # 8 segments, no checkpoint
     assert ref.done and ref.nseg_total == 8
     path = str(tmp_path / "n24.json")
@@ -190,7 +190,7 @@ def test_segmented_run_resumes_to_the_same_bits(ph, tmp_path):
 def test_large_n_haar_ranges_against_oracle(ph, algo, n, c):
     # orders 45..52 sweep each term over two lanes (rows split in halves, odd n
     # padded); short ranges high in the index space against the exact sums
-    a = I.config3_matrix(n)
+    a = I.haar1600_block(n)
     g, d = O.to_gaussian_integers(a)
     scale = Fraction(1, d ** n)
     cc = ph.perm_chunk_log2(n, algo, chunk_log2=c)
@@ -247,7 +247,7 @@ def test_command_line_runs_and_resumes(ph, tmp_path):
     import sys
 
     n = 24
-    a = I.config3_matrix(n)
+    a = I.haar1600_block(n)
     f = tmp_path / "a.npy"
     np.save(f, a)
     ck = tmp_path / "ck.json"

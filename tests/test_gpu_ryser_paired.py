@@ -61,10 +61,10 @@ def test_chunk_lengths_bit_exact(ph, c):
     assert complex(ph.perm_ryser_paired(cuda(a), chunk_log2=c).cpu()) == want
 
 
-def test_config1_haar20_in_place(ph):
+def test_haar400_block20_in_place(ph):
     u = cuda(I.haar(400, 11))
-    a = I.config1_haar20()
-    ex = G.value_for("haar", "config1_haar20", a)
+    a = I.haar400_block20()
+    ex = G.value_for("haar", "haar400_block20", a)
     got = complex(ph.perm_ryser_paired(u[:20, :20]).cpu())
     assert O.rel_err(got, ex) <= ryser_tol(20)
     # the same bits from a contiguous copy, and from a second call
@@ -74,8 +74,8 @@ def test_config1_haar20_in_place(ph):
 
 @pytest.mark.parametrize("n", [22, 26, 30])
 def test_haar_against_stored_exact(ph, n):
-    a = I.config3_matrix(n)
-    ex = G.value_for("haar", f"config3_n{n}", a)
+    a = I.haar1600_block(n)
+    ex = G.value_for("haar", f"haar1600_block_n{n}", a)
     if ex is None:
         pytest.skip(f"no stored exact value for n={n}")
     got = complex(ph.perm_ryser_paired(cuda(a)).cpu())

@@ -104,7 +104,7 @@ def test_full_workload_every_step_against_the_probability_layer(ph):
     # recomputed as Eq. (1) probabilities of the grown patterns (grouped sweeps,
     # an independent path) times their occupation factorials; the sampler's
     # choice must satisfy the decision rule with that step's uniform
-    u_np, ins, _ = I.config5_workload(m=900, n=30, patterns=1)
+    u_np, ins, _ = I.boson_workload(m=900, n=30, patterns=1)
     u = torch.from_numpy(u_np).to("cuda")
     n = len(ins)
     perms, unis = ph.sample_inputs(2, n, 11)

@@ -32,9 +32,9 @@ def run_all(ph, a, b, u, ins, pats):
 
 
 def test_side_stream_gives_the_same_bits(ph):
-    a = cuda(I.config3_matrix(24))
-    b = cuda(I.config4_batch(32, 16))
-    u_np, ins, pats = I.config5_workload(m=200, n=16, patterns=6)
+    a = cuda(I.haar1600_block(24))
+    b = cuda(I.grad_batch_20(32, 16))
+    u_np, ins, pats = I.boson_workload(m=200, n=16, patterns=6)
     u = cuda(u_np)
     ref = [x.cpu() for x in run_all(ph, a, b, u, ins, pats)]
     side = torch.cuda.Stream()
@@ -49,8 +49,8 @@ def test_side_stream_gives_the_same_bits(ph):
 def test_two_streams_in_flight(ph):
     # different work on two streams at once, each checked against its own
     # default-stream result
-    m1 = cuda(I.config4_batch(64, 18))
-    m2 = cuda(I.config3_matrix(26))
+    m1 = cuda(I.grad_batch_20(64, 18))
+    m2 = cuda(I.haar1600_block(26))
     r1 = ph.perm_batched(m1).cpu()
     r2 = ph.perm(m2).cpu()
     s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()

@@ -378,8 +378,8 @@ def test_probability_without_collisions_is_abs_perm_squared():
 
 # ----------------------------------------------------- integer exactness check
 
-def test_config1_integer_matrix_is_certified():
-    c = O.certify_int_exact(I.config1_int12())
+def test_int12_matrix_is_certified():
+    c = O.certify_int_exact(I.int12_matrix())
     assert c["certified"] and c["max_partial_product"] < 2 ** 53 and c["sum_abs_terms"] < 2 ** 53
     assert not O.certify_int_exact(I.all_r(12, 100))["certified"]
 
