@@ -92,7 +92,8 @@ enum {
 /* Per(A) of one n x n matrix into *out (one complex128, device).
  * A: device, row stride lda >= n (elements).  0 <= n <= PH_NMAX.
  * The 2^(n-1) (Glynn) or 2^n (Ryser) terms are cut into contiguous Gray-code
- * chunks, one per GPU lane at a time; see the formulas above. */
+ * chunks, one per GPU lane at a time (one per pair of lanes from n = 45); see
+ * the formulas above. */
 int ph_perm(const ph_c128* A, int32_t n, int64_t lda, ph_c128* out, const ph_opts* opt, void* stream);
 
 /* ph_perm_ryser_paired: *out (device, one complex128) = Per(A) by Ryser's
@@ -101,7 +102,8 @@ int ph_perm(const ph_c128* A, int32_t n, int64_t lda, ph_c128* out, const ph_opt
  * columns (in Gray order here) and takes with each S the term of its
  * complement among all n columns, so every subset is summed once.  A as
  * ph_perm (device, lda >= n), 0 <= n <= 32.  opt: accum and chunk_log2 are
- * used (algo and waves are ignored; a chunk is 2^chunk_log2 loop indices).
+ * used (a chunk is 2^chunk_log2 loop indices); algo and waves are checked as
+ * for ph_perm but do not change the computation.
  * Errors: PH_EINVAL (NULL pointer, lda < n, n < 0, bad options), PH_ERANGE
  * (n > 32), PH_EHIP.  Asynchronous on `stream`; deterministic. */
 int ph_perm_ryser_paired(const ph_c128* A, int32_t n, int64_t lda, ph_c128* out, const ph_opts* opt, void* stream);
