@@ -23,5 +23,14 @@ from .permhip import (  # noqa: F401
     perm_ryser_paired,
     version,
 )
-from . import segments  # noqa: F401
 from .autograd import BosonProbsFn, PermFn, boson_probabilities, permanent  # noqa: F401
+
+
+def __getattr__(name):
+    # the segment runner is also a command line (python -m ...segments), so it
+    # is imported on first use rather than with the package
+    if name == "segments":
+        import importlib
+
+        return importlib.import_module(".segments", __name__)
+    raise AttributeError(f"module {__name__!r} has no attribute {name!r}")
