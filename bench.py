@@ -313,6 +313,9 @@ def precision(ph, dev, large):
             for accum in ("dd", "plain"):
                 v, _ = run(a, algo, accum)
                 row[f"{algo}_{accum}"] = abs(v - exact) / abs(exact)
+        # Ryser in the load-balanced order of Algorithm S3
+        v = complex(ph.perm_ryser_paired(torch.from_numpy(a).to(dev)).cpu())
+        row["ryser_paired_dd"] = abs(v - exact) / abs(exact)
         rows.append(row)
         _log(f"precision: {name} done")
     big = []
@@ -372,6 +375,9 @@ def precision_allr(ph, dev):
             for accum in ("dd", "plain"):
                 v = complex(ph.perm(a, algo=algo, accum=accum).cpu())
                 row[f"{algo}_{accum}"] = abs(v - exact) / abs(exact)
+        if n <= 32:  # Ryser in the load-balanced order of Algorithm S3
+            v = complex(ph.perm_ryser_paired(a).cpu())
+            row["ryser_paired_dd"] = abs(v - exact) / abs(exact)
         row["paper_bbfg"] = printed.get(("bbfg", n, r))
         row["paper_ryser"] = printed.get(("ryser", n, r))
         rows.append(row)
