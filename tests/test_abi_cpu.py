@@ -264,3 +264,14 @@ def test_trace_ranges_switch_on_without_side_effects(L):
     env = dict(os.environ, PERMHIP_ROCTX="1")
     r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
     assert r.returncode == 0 and r.stdout.strip() == "ok", r.stderr
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    # no CPU fallback: without libpermhip.so the binding raises instead of
+    # computing anything elsewhere
+    from paper_1606_05836_amd import permhip as P
+
+    monkeypatch.setattr(P, "_lib", None)
+    monkeypatch.setattr(P, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libpermhip.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        P.lib()
