@@ -537,7 +537,15 @@ def main():
         "result": [result.real, result.imag],
     }
     if not args.no_extras:
+        # the FMA-only microbenchmark (the paper's own efficiency reference)
+        # and the shader clock it sustains, right after the sweep's steps
+        gflops, mhz = ph.fp64_peak(device=dev)
+        _log(f"fp64 FMA microbenchmark: {gflops / 1e3:.1f} TFLOP/s at {mhz:.0f} MHz")
         line["extras"] = extras(ph, dev, stream)
+        line["extras"]["fp64_fma_peak"] = {
+            "tflops": gflops / 1e3, "mhz": mhz, "frac_of_spec_peak": gflops / 1e3 / PEAK_FP64_VECTOR_TFLOPS,
+            "n40_sweep_frac_of_it": achieved / (gflops / 1e3) if gflops > 0 else None,
+        }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(a_host, n)
     print(json.dumps(line), flush=True)
