@@ -12,8 +12,10 @@ same line carries, under "extras", the other two figures of the metric --
 batched permanents/s (4096 matrices, n uniform in 16..26, one graph replay)
 and the backward/forward time ratio (1024 matrices of n = 20) -- the latency
 of one small call (20 x 20 and 12 x 12), one 2^37-term share of n = 48 and
-n = 50, and the boson-sampling workload (U 900 x 900, 30 photons, 256
-collision patterns): probabilities/s, the gradient's cost and samples/s.
+n = 50, Ryser in the order of Algorithm S3 against plain Ryser at n = 30,
+the boson-sampling workload (U 900 x 900, 30 photons, 256 collision
+patterns): probabilities/s, the gradient's cost and samples/s, and the
+FMA-only microbenchmark with the shader clock it sustains.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 40]
                        [--no-cpu] [--no-extras] [--copy-probe MiB]
