@@ -367,8 +367,12 @@ def to_complex(x) -> complex:
 
 
 def rel_err(value, exact) -> float:
-    """|value - exact| / |exact| with the difference taken in exact rational
-    arithmetic (value is converted exactly); |exact| = 0 gives |value|."""
+    """Relative error of a computed permanent, the measure of the paper's
+    Supplementary error tables (the distance to the theory value over the
+    theory value's modulus): |value - exact| / |exact|, with |.| the complex
+    modulus.  The difference and the quotient are taken in exact rational
+    arithmetic (value is converted exactly) and only the square root is
+    rounded; |exact| = 0 gives |value|, the absolute error."""
     vr, vi = _as_rational_parts(value)
     er, ei = exact
     num = (vr - er) ** 2 + (vi - ei) ** 2
@@ -395,20 +399,24 @@ def certify_int_exact(a, ryser: bool = False) -> dict:
 
     Exactness holds when every intermediate is an integer of magnitude below
     2^53.  With |x|_1 = |Re x| + |Im x| (which bounds both parts and satisfies
-    |xy|_1 <= |x|_1 |y|_1), two bounds suffice:
-      * every partial product of row sums: max over terms of
-        prod_i max(1, |r_i|_1) < 2^53;
+    |xy|_1 <= |x|_1 |y|_1), three bounds suffice:
+      * every partial sum met while a row sum is formed from scratch, from
+        entries a_ij or 2 a_ij with any signs, in any order:
+        2 max_i sum_j |a_ij|_1 < 2^53;
+      * every partial product of row sums (and every row sum reached by
+        steps): max over terms of prod_i max(1, |r_i|_1) < 2^53;
       * every partial sum of terms, in any order: sum over terms of
         |term|_1 < 2^53.
     The walk is Eq. (S2) in Gray order (or Eq. (S1) over all subsets when
-    ``ryser``).  Returns the two bounds and whether both hold.
+    ``ryser``).  Returns the three bounds and whether all hold.
     """
     g, d = to_gaussian_integers(a)
     if d != 1:
         return {"certified": False, "reason": "entries are not integers"}
     n = len(g)
     if n == 0:
-        return {"certified": True, "max_partial_product": 1, "sum_abs_terms": 1}
+        return {"certified": True, "seed_partial_sums": 0, "max_partial_product": 1, "sum_abs_terms": 1}
+    seed_bound = 2 * max(sum(abs(x[0]) + abs(x[1]) for x in row) for row in g)
     max_pp = 0
     sum_abs = 0
     if ryser:
@@ -433,5 +441,5 @@ def certify_int_exact(a, ryser: bool = False) -> dict:
             p = _prod(rs)
             sum_abs += abs(p[0]) + abs(p[1])
     lim = 1 << 53
-    return {"certified": max_pp < lim and sum_abs < lim,
-            "max_partial_product": max_pp, "sum_abs_terms": sum_abs}
+    return {"certified": seed_bound < lim and max_pp < lim and sum_abs < lim,
+            "seed_partial_sums": seed_bound, "max_partial_product": max_pp, "sum_abs_terms": sum_abs}

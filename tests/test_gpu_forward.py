@@ -69,15 +69,19 @@ def test_int12_matrix_bit_exact(ph, algo, accum):
 
 @pytest.mark.parametrize("algo", ["glynn", "ryser"])
 def test_integer_matrices_bit_exact_all_small_n(ph, algo):
+    checked = 0
     for n in range(1, 15):
         a = gauss_int(n, 31 * n, -2, 2)
-        if not O.certify_int_exact(a, ryser=(algo == "ryser"))["certified"]:
-            continue
+        # every size must be certified exact in binary64: a size the
+        # certificate rejected would silently drop out of the bit-exact bar
+        assert O.certify_int_exact(a, ryser=(algo == "ryser"))["certified"], n
+        checked += 1
         want = c_exact(O.perm_exact(a))
         nb = n - 1 if algo == "glynn" else n
         for c in sorted({0, 1, 4, 5, nb}):
             got = run(ph, a, algo=algo, chunk_log2=c)
             assert got == want, (n, c, got, want)
+    assert checked == 14
 
 
 def test_empty_and_one_by_one(ph):

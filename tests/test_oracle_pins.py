@@ -381,7 +381,108 @@ def test_probability_without_collisions_is_abs_perm_squared():
 def test_int12_matrix_is_certified():
     c = O.certify_int_exact(I.int12_matrix())
     assert c["certified"] and c["max_partial_product"] < 2 ** 53 and c["sum_abs_terms"] < 2 ** 53
+    assert c["seed_partial_sums"] < 2 ** 53
     assert not O.certify_int_exact(I.all_r(12, 100))["certified"]
+
+
+def _cancelling_rows(a, b):
+    """Rows (a, 0, 0, 0), (b, 0, 0, 0), (1, 1, 0, 0), (1, -1, 0, 0).  For every
+    delta of Eq. (S2) the last two row sums are 1 + delta_1 and 1 - delta_1,
+    one of them 0: every term is 0 (so is the sum of |term|, and Per), while
+    the partial product a * b * 2 is reached.  Seeds stay small."""
+    m = np.zeros((4, 4), np.complex128)
+    m[0, 0], m[1, 0] = a, b
+    m[2, :2] = (1, 1)
+    m[3, :2] = (1, -1)
+    return m
+
+
+def test_certificate_partial_product_boundary():
+    ok = O.certify_int_exact(_cancelling_rows(2 ** 26, 2 ** 26 - 1))
+    assert ok["certified"] and ok["max_partial_product"] == 2 ** 53 - 2 ** 27
+    assert ok["sum_abs_terms"] == 0 and ok["seed_partial_sums"] == 2 ** 27
+    bad = O.certify_int_exact(_cancelling_rows(2 ** 26, 2 ** 26))
+    assert not bad["certified"] and bad["max_partial_product"] == 2 ** 53
+    assert bad["sum_abs_terms"] == 0 and bad["seed_partial_sums"] == 2 ** 27
+    assert O.perm_exact(_cancelling_rows(2 ** 26, 2 ** 26)) == (0, 0)
+
+
+def test_certificate_term_sum_boundary():
+    # diag(a, b): both BB/FG terms equal ab (sign and row sum flip together),
+    # so the sum of |term|_1 is 2|ab|_1 while every partial product is
+    # |a|_1 |b|_1 and the seeds stay small
+    def d(a, b):
+        return np.diag([a, b]).astype(np.complex128)
+    ok = O.certify_int_exact(d(2 ** 26, 2 ** 26 - 1))
+    assert ok["certified"] and ok["sum_abs_terms"] == 2 ** 53 - 2 ** 27 and ok["max_partial_product"] < 2 ** 52
+    bad = O.certify_int_exact(d(2 ** 26, 2 ** 26))
+    assert not bad["certified"] and bad["sum_abs_terms"] == 2 ** 53 and bad["max_partial_product"] == 2 ** 52
+    assert bad["seed_partial_sums"] == 2 ** 27
+    # the imaginary part counts in |.|_1 like the real one: |2^25 (1 + i)|_1 = 2^26
+    bad_i = O.certify_int_exact(d(2 ** 26, 2 ** 25 * (1 + 1j)))
+    assert not bad_i["certified"] and bad_i["sum_abs_terms"] == 2 ** 53 and bad_i["max_partial_product"] == 2 ** 52
+
+
+def test_certificate_seed_boundary():
+    # one row [x, -x]: its BB/FG row sums are 0 or 2x and the terms cancel
+    # against the zero row below, but forming 2x from scratch passes through
+    # partial sums up to 2 sum_j |a_ij|_1 = 4x in the worst order
+    def m(x):
+        return np.array([[x, -x], [0, 0]], dtype=np.complex128)
+    assert O.certify_int_exact(m(2 ** 51 - 1))["seed_partial_sums"] == 2 ** 53 - 4
+    assert O.certify_int_exact(m(2 ** 51 - 1))["certified"]
+    assert not O.certify_int_exact(m(2 ** 51))["certified"]
+
+
+# --------------------------------------------------- the relative-error checker
+
+def _rel_err_cases():
+    """(value, exact, expected) worked by hand.  RelErr is the measure of the
+    paper's Supplementary error tables: |Per - Per_theory| / |Per_theory|,
+    with the complex modulus."""
+    third = Fraction(1, 3)
+    return [
+        # real part off by 2^-33 of 1: relative error 2^-33 exactly
+        (1.0 + 2.0 ** -33, (Fraction(1), Fraction(0)), 2.0 ** -33),
+        # an offset of 3 + 4i on the real value 10: |3 + 4i| / 10 = 0.5
+        (13.0 + 4.0j, (Fraction(10), Fraction(0)), 0.5),
+        # a purely imaginary offset on a complex exact value 3 + 4i: 2^-20 / 5
+        (3.0 + (4.0 + 2.0 ** -20) * 1j, (Fraction(3), Fraction(4)), 2.0 ** -20 / 5),
+        # a unit offset along the exact value's own direction: 1 / |3 + 4i|
+        (3.6 + 4.8j, (Fraction(3), Fraction(4)), None),
+        # exact value 0: the absolute error |3 + 4i| = 5
+        (3.0 + 4.0j, (Fraction(0), Fraction(0)), 5.0),
+        # an exact rational: the binary64 nearest 1/3 is 1/3 - 1/(3 2^54),
+        # so the relative error is 2^-54 exactly
+        (1.0 / 3.0, (third, Fraction(0)), 2.0 ** -54),
+        # no error at all, exact value given as Fractions of a binary64 input
+        (0.1 - 0.7j, (Fraction(0.1), Fraction(-0.7)), 0.0),
+    ]
+
+
+def _rel_err_pins_hold(fn) -> bool:
+    for value, exact, want in _rel_err_cases():
+        got = fn(value, exact)
+        if want is None:
+            # 3.6 + 4.8i is not exactly 1.2 (3 + 4i) in binary64; the exact
+            # value of the offset is computed from the stored doubles
+            d = (Fraction(3.6) - 3) ** 2 + (Fraction(4.8) - 4) ** 2
+            want = math.sqrt(float(d / 25))
+            if abs(want - 0.2) > 1e-15:
+                return False
+        if want == 0.0:
+            if got != 0.0:
+                return False
+        elif not abs(got - want) <= 2e-16 * want:
+            return False
+    return True
+
+
+def test_rel_err_on_hand_computed_cases():
+    assert _rel_err_pins_hold(O.rel_err)
+    for value, exact, want in _rel_err_cases():
+        if want is not None and want != 0.0 and math.log2(want).is_integer():
+            assert O.rel_err(value, exact) == want  # powers of two come out exactly
 
 
 # ------------------------------------------------------------- mutation tests
@@ -425,3 +526,73 @@ def test_mutation_wrong_fixed_delta_is_caught(monkeypatch):
 def test_mutation_transposed_operand_in_complex_product_is_caught(monkeypatch):
     # (a+ib)(c+id) with the imaginary part's operands swapped wrongly
     assert _pins_fail(monkeypatch, "_cmul", lambda x, y: (x[0] * y[0] - x[1] * y[1], x[0] * y[0] + x[1] * y[1]))
+
+
+# mutants of the relative-error checker and of the integer certificate: each
+# plausible slip must break a pin above
+
+def _mutant_rel_err_no_sqrt(value, exact):
+    vr, vi = OX._as_rational_parts(value)
+    num = (vr - exact[0]) ** 2 + (vi - exact[1]) ** 2
+    den = exact[0] ** 2 + exact[1] ** 2
+    return float(num / den) if den else float(num)
+
+
+def _mutant_rel_err_over_value(value, exact):
+    vr, vi = OX._as_rational_parts(value)
+    num = (vr - exact[0]) ** 2 + (vi - exact[1]) ** 2
+    den = vr * vr + vi * vi
+    return math.sqrt(float(num / den)) if den else math.sqrt(float(num))
+
+
+def _mutant_rel_err_real_only(value, exact):
+    vr, _ = OX._as_rational_parts(value)
+    den = exact[0] ** 2 + exact[1] ** 2
+    return math.sqrt(float((vr - exact[0]) ** 2 / den)) if den else abs(float(vr - exact[0]))
+
+
+def _mutant_rel_err_in_binary64(value, exact):
+    ex = complex(float(exact[0]), float(exact[1]))
+    return abs(complex(value) - ex) / abs(ex) if ex else abs(complex(value))
+
+
+@pytest.mark.parametrize("mutant", [_mutant_rel_err_no_sqrt, _mutant_rel_err_over_value, _mutant_rel_err_real_only,
+                                    _mutant_rel_err_in_binary64])
+def test_mutation_rel_err_is_caught(mutant):
+    assert not _rel_err_pins_hold(mutant)
+
+
+def _certificate_pins_hold(monkeypatch, mutant_source):
+    """Run the boundary pins of the integer certificate against a mutated copy
+    of it (a textual edit of its source, executed in the oracle's namespace)."""
+    import inspect
+
+    src = inspect.getsource(OX.certify_int_exact)
+    mutated = mutant_source(src)
+    assert mutated != src, "mutation did not apply"
+    ns = dict(vars(OX))
+    exec(compile(mutated, "<mutant>", "exec"), ns)
+    monkeypatch.setattr(O, "certify_int_exact", ns["certify_int_exact"])
+    try:
+        test_certificate_partial_product_boundary()
+        test_certificate_term_sum_boundary()
+        test_certificate_seed_boundary()
+    except AssertionError:
+        return False
+    return True
+
+
+@pytest.mark.parametrize("edit", [
+    lambda s: s.replace("seed_bound < lim and ", ""),                    # seed bound dropped
+    lambda s: s.replace("max_pp < lim and ", ""),                        # product bound dropped
+    lambda s: s.replace(" and sum_abs < lim", ""),                       # term-sum bound dropped
+    lambda s: s.replace("max_pp < lim", "max_pp <= lim"),                # off by one at 2^53
+    lambda s: s.replace("abs(x[0]) + abs(x[1])", "abs(x[0])").replace("abs(p[0]) + abs(p[1])", "abs(p[0])"),
+    # (imaginary parts ignored)
+])
+def test_mutation_certificate_is_caught(monkeypatch, edit):
+    assert not _certificate_pins_hold(monkeypatch, edit)
+
+
+def test_certificate_pins_hold_unmutated(monkeypatch):
+    assert _certificate_pins_hold(monkeypatch, lambda s: s + "\n")
