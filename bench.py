@@ -14,8 +14,9 @@ and the backward/forward time ratio (1024 matrices of n = 20) -- the latency
 of one small call (20 x 20 and 12 x 12), one 2^37-term share of n = 48 and
 n = 50, Ryser in the order of Algorithm S3 against plain Ryser at n = 30,
 the boson-sampling workload (U 900 x 900, 30 photons, 256 collision
-patterns): probabilities/s, the gradient's cost and samples/s, and the
-FMA-only microbenchmark with the shader clock it sustains.
+patterns): probabilities/s, the gradient's cost and samples/s, the n = 40
+sweep with the plain outer sum and one whole n = 44 permanent (config3), and
+the FMA-only microbenchmark with the shader clock it sustains.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 40]
                        [--no-cpu] [--no-extras] [--copy-probe MiB]
@@ -242,6 +243,43 @@ def extras(ph, dev, stream):
         "probs_ms": pf, "probs_per_s": len(pats) / (pf / 1e3), "grad_ms": pg, "grad_fwd_ratio": pg / pf,
         "samples_64_ms": ps, "samples_per_s": 64 / (ps / 1e3),
     }
+    return res
+
+
+def config3(ph, dev, stream, a40, dd40):
+    """The n = 40 / 44 workload beside the headline line: n = 40 with the
+    plain binary64 outer sum (rate, and its result's relative difference from
+    the double-double one), one whole n = 44 permanent with the double-double
+    sum (2^43 terms, about 75 s) with its rate and fraction of the FP64 peak,
+    and both orders' fraction of the instruction-mix ceiling: a term needs at
+    least 6n - 2 FP64 instructions for its 8n - 4 flops, so at most
+    (8n - 4) / (2 (6n - 2)) of the peak at any clock."""
+    import torch
+
+    import inputs
+
+    def ceiling(n):
+        return (8 * n - 4) / (2 * (6 * n - 2))
+
+    res = {}
+    out = torch.empty((), dtype=torch.complex128, device=dev)
+    ms = _median(_event_ms(lambda: ph.perm(a40, accum="plain", out=out), 2, stream))
+    plain = complex(out.cpu())
+    frac = (1 << 39) * flops_per_term(40) / (ms / 1e3) / 1e12 / PEAK_FP64_VECTOR_TFLOPS
+    res["n40_plain"] = {"ms": ms, "terms_per_s": 2.0 ** 39 / (ms / 1e3), "frac_fp64_peak": frac,
+                        "result": [plain.real, plain.imag], "rel_diff_plain_vs_dd": abs(plain - dd40) / abs(dd40)}
+    _log(f"n=40 plain: {ms:.1f} ms, |plain - dd| / |dd| = {res['n40_plain']['rel_diff_plain_vs_dd']:.2e}")
+    a44 = torch.from_numpy(inputs.haar1600_block(44)).to(dev)
+    _log("n=44 dd: one whole permanent (2^43 terms) ...")
+    ms44 = _event_ms(lambda: ph.perm(a44, out=out), 1, stream)[0]
+    v44 = complex(out.cpu())
+    frac44 = (1 << 43) * flops_per_term(44) / (ms44 / 1e3) / 1e12 / PEAK_FP64_VECTOR_TFLOPS
+    res["n44_dd"] = {"workload": "permanent of the n=44 submatrix of Haar(1600, seed 31) (rows seed 76, first 44 "
+                                 "columns), BB/FG, dd outer sum",
+                     "ms": ms44, "terms_per_s": 2.0 ** 43 / (ms44 / 1e3), "frac_fp64_peak": frac44,
+                     "frac_of_mix_ceiling": frac44 / ceiling(44), "result": [v44.real, v44.imag]}
+    _log(f"n=44 dd: {ms44 / 1e3:.1f} s, {frac44:.3f} of the FP64 peak")
+    res["mix_ceiling"] = {"n40": ceiling(40), "n44": ceiling(44)}
     return res
 
 
@@ -544,6 +582,10 @@ def main():
         gflops, mhz = ph.fp64_peak(device=dev)
         _log(f"fp64 FMA microbenchmark: {gflops / 1e3:.1f} TFLOP/s at {mhz:.0f} MHz")
         line["extras"] = extras(ph, dev, stream)
+        if n == 40 and args.accum == "dd":
+            line["extras"]["config3"] = config3(ph, dev, stream, a, result)
+            line["extras"]["config3"]["n40_dd_frac_of_mix_ceiling"] = \
+                achieved / PEAK_FP64_VECTOR_TFLOPS / line["extras"]["config3"]["mix_ceiling"]["n40"]
         line["extras"]["fp64_fma_peak"] = {
             "tflops": gflops / 1e3, "mhz": mhz, "frac_of_spec_peak": gflops / 1e3 / PEAK_FP64_VECTOR_TFLOPS,
             "n40_sweep_frac_of_it": achieved / (gflops / 1e3) if gflops > 0 else None,

@@ -55,6 +55,7 @@ enum { PH_GLYNN = 0, PH_RYSER = 1 };
 enum { PH_ACC_DD = 0, PH_ACC_PLAIN = 1 };
 #define PH_FLAG_UNGROUPED 1u
 #define PH_FLAG_UNSORTED 2u
+#define PH_FLAG_DU_FULL 4u
 
 /* Options; pass NULL for the defaults (Glynn, double-double, tuned sizes; the
  * environment variable PERMHIP_ACCUM=plain or =dd sets the default
@@ -62,13 +63,18 @@ enum { PH_ACC_DD = 0, PH_ACC_PLAIN = 1 };
  *   algo        PH_GLYNN or PH_RYSER
  *   accum       PH_ACC_DD or PH_ACC_PLAIN
  *   chunk_log2  log2 of the Gray-code chunk one lane walks between re-seeds
- *               of its row sums; 0 = library choice.  Values outside the
- *               range the kernel supports for n are clamped.
+ *               of its row sums; 0 = library choice, < 0 is PH_EINVAL.
+ *               Values above PH_CHUNK_LOG2_MAX, or outside the range the
+ *               kernel supports for n (at least the few steps of one
+ *               unrolled block, at most the whole term range), are clamped
+ *               (ph_perm_chunk_log2 reports the value used).
  *   waves       wavefronts per SIMD to launch (1..8); 0 = library choice
  *   flags       0, or PH_FLAG_UNGROUPED (ph_boson_probs only: one full sweep
  *               per pattern instead of the multiplicity-grouped sweeps), or
  *               PH_FLAG_UNSORTED (ph_boson_sample only: out_modes in the
- *               order the photons were placed, r_1..r_n) */
+ *               order the photons were placed, r_1..r_n), or PH_FLAG_DU_FULL
+ *               (ph_boson_probs_grad only: the gradient with respect to all
+ *               of U, see there); flags combine with | */
 typedef struct {
   int32_t algo;
   int32_t accum;
@@ -87,6 +93,10 @@ enum {
 };
 
 #define PH_NMAX 52      /* largest n of ph_perm / batched plans */
+/* Largest chunk_log2 any call uses: steps inside a chunk are counted in 32-bit
+ * integers, and the incremental row sums drift by up to about 2^c roundings
+ * between re-seeds, so longer chunks buy nothing. */
+#define PH_CHUNK_LOG2_MAX 24
 #define PH_NMAX_GRAD 32 /* largest n of ph_perm_grad and the boson layer */
 
 /* Per(A) of one n x n matrix into *out (one complex128, device).
@@ -163,11 +173,27 @@ int ph_perm_batched(const ph_c128* A_packed, const int64_t* offsets_host, const 
  * (one hipGraphLaunch; the kernel arguments are updated in place when the
  * pointers differ from the last call); matrices of order >= 45 (2^44 terms or
  * more each) are then swept one at a time by the ph_perm kernels.  A plan is bound to the device that
- * was current at creation and may be used from one thread at a time. */
+ * was current at creation and may be used from one thread at a time.  Its
+ * executions run one after another, also across streams: an execution on a
+ * stream other than the previous one's first waits for that one (the plan's
+ * counters and partial sums are its own, not per stream). */
 int ph_plan_create(const int32_t* n_host, const int64_t* offsets_host, int64_t batch, const ph_opts* opt,
                    void* stream, void** plan);
 int ph_plan_execute(void* plan, const ph_c128* A_packed, ph_c128* out, void* stream);
 int ph_plan_destroy(void* plan);
+
+/* ph_plan_shape: the sweep shape a plan uses for its matrices of order n --
+ * *chunk_log2 (host) the log2 chunk length, *waves (host) the wavefronts per
+ * SIMD of that size bucket's sweep (0 = as many as fit).  With
+ * opt->chunk_log2 == 0 the plan takes both from the autotuner, which times
+ * every (chunk length, waves) pair on a synthetic batch of about 2^27 terms
+ * per order (orders of more than 2^27 terms take c = min(12, n - 9) and full
+ * occupancy) and remembers the fastest per (library build, device, order,
+ * formula, accumulation) for the process, and across processes in the file
+ * named by the environment variable PERMHIP_TUNE_CACHE (entries of other
+ * builds are ignored).  opt->waves > 0 overrides the tuned waves.
+ * PH_EINVAL if the plan holds no matrix of order n. */
+int ph_plan_shape(const void* plan, int32_t n, int32_t* chunk_log2, int32_t* waves);
 
 /* Gradient of the permanent.  A holds `batch` contiguous n x n matrices
  * (batch * n * n complex128).  For each matrix the library forms
@@ -203,10 +229,14 @@ int ph_boson_probs(const ph_c128* U, int32_t m, int64_t ldu, const int32_t* in_m
                    const int32_t* patterns, int64_t n_patterns, double* probs, const ph_opts* opt, void* stream);
 
 /* Gradient of L = sum_p w_p Pr[S -> T_p] with respect to the columns of U
- * used by the inputs: dU (device, m x n, row stride lddu) receives
+ * used by the inputs: dU (device, m x n, row stride lddu >= n) receives
  * dL/dU[:, in_modes[k]] for k = 0..n-1 (column k of dU belongs to input
  * photon k; PyTorch's conjugate-Wirtinger convention), accumulated over all
- * patterns and repeated rows in a fixed order.  weights (device, n_patterns
+ * patterns and repeated rows in a fixed order.  With PH_FLAG_DU_FULL in
+ * opt->flags, dU is instead the m x m gradient with respect to all of U
+ * (row stride lddu >= m): column j holds the sum, in increasing k, of the
+ * per-photon columns of the photons k with in_modes[k] == j, and the columns
+ * of modes without an input photon are 0.  weights (device, n_patterns
  * doubles) or NULL for w_p = 1.  probs (device, nullable) receives the
  * probabilities as a by-product.  dU is overwritten, not accumulated into. */
 int ph_boson_probs_grad(const ph_c128* U, int32_t m, int64_t ldu, const int32_t* in_modes, int32_t n,

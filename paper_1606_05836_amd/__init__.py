@@ -4,6 +4,9 @@ The computation lives in libpermhip.so (C ABI: include/permhip.h); this
 package is its Python binding plus a torch.autograd.Function wrapper.
 """
 from .permhip import (  # noqa: F401
+    PH_CHUNK_LOG2_MAX,
+    PH_NMAX,
+    PH_NMAX_GRAD,
     PermhipError,
     Plan,
     boson_probs,

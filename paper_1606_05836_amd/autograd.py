@@ -45,8 +45,8 @@ class BosonProbsFn(torch.autograd.Function):
     """Eq. (1) probabilities Pr[S -> T_p] as a differentiable function of U.
 
     Backward: ph_boson_probs_grad with the upstream gradient as the pattern
-    weights gives dL/dU[:, S_k] per input photon k; photons that share an
-    input mode add into the same column of U's gradient."""
+    weights and the m x m form of dU (PH_FLAG_DU_FULL): photons that share an
+    input mode add into the same column of U's gradient, in the library."""
 
     @staticmethod
     def forward(ctx, u: torch.Tensor, in_modes, patterns) -> torch.Tensor:
@@ -58,10 +58,7 @@ class BosonProbsFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g: torch.Tensor):
         (u,) = ctx.saved_tensors
-        _, du = _p.boson_probs_grad(u, ctx.in_modes, ctx.patterns, weights=g)
-        cols = torch.as_tensor([int(x) for x in ctx.in_modes], dtype=torch.int64, device=u.device)
-        gu = torch.zeros_like(u)
-        gu.index_add_(1, cols, du)
+        _, gu = _p.boson_probs_grad(u, ctx.in_modes, ctx.patterns, weights=g, full=True)
         return gu, None, None
 
 

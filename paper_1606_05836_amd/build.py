@@ -12,6 +12,7 @@ usage: python -m paper_1606_05836_amd.build [--jobs N]
 from __future__ import annotations
 
 import argparse
+import hashlib
 import os
 import re
 import shutil
@@ -41,6 +42,18 @@ RANGES = [(1, 16), (17, 24), (25, 32), (33, 40), (41, 44), (45, 52)]
 RANGED = ("sweep_single.hip", "sweep_batched.hip")  # compiled once per size range
 
 
+def build_id() -> str:
+    """Hash of the kernel and header sources: the autotuner's cache entries
+    are valid for one build id only."""
+    h = hashlib.sha256()
+    for d in (CSRC, os.path.join(ROOT, "include")):
+        for name in sorted(os.listdir(d)):
+            if name.endswith((".hip", ".cpp", ".hpp", ".h")):
+                with open(os.path.join(d, name), "rb") as f:
+                    h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
 def units():
     """(output object, source, extra flags)"""
     u = []
@@ -53,12 +66,14 @@ def units():
     return u
 
 
-_REMARK = re.compile(r"remark: .*?(Function Name|VGPRs Spill|SGPRs Spill|AGPRs|VGPRs|Occupancy \[waves/SIMD\]): (\S+)")
+_REMARK = re.compile(r"remark: .*?(Function Name|VGPRs Spill|SGPRs Spill|AGPRs|VGPRs|ScratchSize \[bytes/lane\]|"
+                     r"Occupancy \[waves/SIMD\]): (\S+)")
 
 
 def _compile(unit):
     obj, src, extra = unit
-    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", os.path.join(OUT, obj)]
+    cmd = [HIPCC, *FLAGS, f'-DPH_BUILD_ID="{build_id()}"', *extra, "-c", os.path.join(CSRC, src),
+           "-o", os.path.join(OUT, obj)]
     p = subprocess.run(cmd, capture_output=True, text=True)
     return unit, p.returncode, p.stdout + p.stderr
 
@@ -112,11 +127,14 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
         return True
 
     # kernels that read resident columns with DPP: no spill code of any kind
-    # (AGPR copies included) is allowed there
+    # (AGPR copies included) is allowed there, and no per-lane array may have
+    # been left in scratch memory (a register array the compiler could not
+    # keep in registers, e.g. one indexed through a merged pointer)
     bad = [k for k, v in report.items() if ("sweep" in k or "k_minors" in k or "k_gradILi" in k) and _uses_dpp(k) and (
-        v.get("VGPRs Spill", "0") != "0" or v.get("SGPRs Spill", "0") != "0" or v.get("AGPRs", "0") != "0")]
+        v.get("VGPRs Spill", "0") != "0" or v.get("SGPRs Spill", "0") != "0" or v.get("AGPRs", "0") != "0"
+        or v.get("ScratchSize [bytes/lane]", "0") != "0")]
     if bad:
-        raise RuntimeError("sweep kernels spill registers: " + ", ".join(bad[:8]))
+        raise RuntimeError("sweep kernels spill registers or use scratch: " + ", ".join(bad[:8]))
     objs = [os.path.join(OUT, u[0]) for u in us]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-ldl"]

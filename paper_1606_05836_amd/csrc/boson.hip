@@ -95,6 +95,30 @@ __global__ void k_boson_scatter(const double2* __restrict__ gA, const double2* _
   du[(int64_t)r * lddu + k] = make_double2(sr, si);
 }
 
+// Input modes by value (n <= PH_NMAX_GRAD), for the fold below.
+struct InModes {
+  int32_t v[PH_NMAX_GRAD];
+};
+
+// dU[r][j] = sum over the photons k with in_modes[k] == j, in increasing k,
+// of dUn[r][k] (the per-photon columns); columns no photon uses get 0.  Every
+// entry of the m x m output is written.
+__global__ void k_boson_fold_photons(const double2* __restrict__ dun, int n, InModes in, int m,
+                                     double2* __restrict__ du, int64_t lddu) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)m * m) return;
+  const int r = (int)(t / m), j = (int)(t % m);
+  double sr = 0.0, si = 0.0;
+  for (int k = 0; k < n; ++k) {
+    if (in.v[k] == j) {
+      const double2 x = dun[(int64_t)r * n + k];
+      sr += x.x;
+      si += x.y;
+    }
+  }
+  du[(int64_t)r * lddu + j] = make_double2(sr, si);
+}
+
 static int check_boson_args(const ph_c128* U, int32_t m, int64_t ldu, const int32_t* in_modes, int32_t n,
                             const int32_t* patterns, int64_t npat, int nmax) {
   if (m < 1) return fail(PH_EINVAL, "m=%d < 1", m);
@@ -175,7 +199,7 @@ int upload(hipStream_t st, void* dst, const Piece* pc, int npc) {
 }
 
 // Device buffers of one boson call, in workspace slot 1 of the stream (the
-// permanent kernels own slot 0).  Layout: in_modes | patterns | [rowstart |
+// permanent kernels own WS_SWEEP).  Layout: in_modes | patterns | [rowstart |
 // rowlist] | gathered batch | perms | [gA | gperm].
 struct BosonBufs {
   int32_t* d_in;
@@ -213,7 +237,7 @@ static int boson_setup(hipStream_t st, const ph_c128* U, int32_t m, int64_t ldu,
   off[7] = off[6] + (grad ? up256((size_t)(npat * n * n) * sizeof(double2)) : 0);
   off[8] = off[7] + (grad ? up256((size_t)npat * sizeof(double2)) : 0);
   void* ws = nullptr;
-  int rc = workspace_slot(st, std::max<size_t>(off[8], 256), 1, &ws);
+  int rc = workspace_slot(st, std::max<size_t>(off[8], 256), WS_BOSON, &ws);
   if (rc) return rc;
   char* q = static_cast<char*>(ws);
   b->d_in = reinterpret_cast<int32_t*>(q + off[0]);
@@ -391,7 +415,7 @@ static int boson_probs_grouped(hipStream_t st, const ph_c128* U, int64_t ldu, co
   plan_sweeps(patterns, n, npat, o.ungrouped, &sw);
   const int64_t V = (int64_t)sw.w.size();
   std::vector<int32_t> ns(V, n);
-  // device layout in workspace slot 2 (the first NP_UP entries are uploaded)
+  // device layout in workspace slot WS_BOSON_GROUPED (the first NP_UP entries are uploaded)
   enum { P_IN, P_VCOL, P_VNCOLS, P_VCOEF, P_VNCOEF, P_COLM, P_COLLM, P_PV, P_PAT, P_COEFS, P_W, P_TABOFF, NP_UP,
          B_VOUT = NP_UP, B_PERMS, NB_ALL };
   auto one = [](size_t x) { return std::max<size_t>(x, 1); };
@@ -410,7 +434,7 @@ static int boson_probs_grouped(hipStream_t st, const ph_c128* U, int64_t ldu, co
   off[0] = 0;
   for (int q = 0; q < NB_ALL; ++q) off[q + 1] = off[q] + up256(sz[q]);
   void* ws = nullptr;
-  int rc = workspace_slot(st, off[NB_ALL], 2, &ws);
+  int rc = workspace_slot(st, off[NB_ALL], WS_BOSON_GROUPED, &ws);
   if (rc) return rc;
   char* d = static_cast<char*>(ws);
   auto I32 = [&](int q) { return reinterpret_cast<int32_t*>(d + off[q]); };
@@ -600,7 +624,7 @@ static int boson_grad_grouped(hipStream_t st, const ph_c128* U, int32_t m, int64
     std::vector<int32_t> fill(mstart.begin(), mstart.end() - 1);
     for (int64_t e = 0; e < E; ++e) mlist[fill[ent_mode[e]]++] = (int32_t)e;
   }
-  // device layout (workspace slot 2)
+  // device layout (workspace slot WS_BOSON_GROUPED)
   auto one = [](size_t x) { return std::max<size_t>(x, 1); };
   enum { P_IN, P_PAT, P_VCOL, P_VCOEF, P_VNCOEF, P_COLM, P_COLLM, P_PV, P_VLIST, P_VPOS, P_CSTART, P_CSTRIDE,
          P_ENTPAT, P_MSTART, P_MLIST, P_COEFS, P_W, P_CCOEF, P_CPOS, NP_UP,
@@ -631,7 +655,7 @@ static int boson_grad_grouped(hipStream_t st, const ph_c128* U, int32_t m, int64
   off[0] = 0;
   for (int q = 0; q < NB_ALL; ++q) off[q + 1] = off[q] + up256(sz[q]);
   void* ws = nullptr;
-  int rc = workspace_slot(st, off[NB_ALL], 2, &ws);
+  int rc = workspace_slot(st, off[NB_ALL], WS_BOSON_GROUPED, &ws);
   if (rc) return rc;
   char* d = static_cast<char*>(ws);
   auto I32 = [&](int q) { return reinterpret_cast<int32_t*>(d + off[q]); };
@@ -691,6 +715,12 @@ static int boson_grad_grouped(hipStream_t st, const ph_c128* U, int32_t m, int64
 
 using namespace ph;
 
+namespace ph {
+static int boson_probs_grad_cols(hipStream_t st, const ph_c128* U, int32_t m, int64_t ldu, const int32_t* in_modes,
+                                 int32_t n, const int32_t* patterns, int64_t n_patterns, const double* weights,
+                                 double* probs, ph_c128* dU, int64_t lddu, const Opts& o, int cus);
+}  // namespace ph
+
 extern "C" int ph_boson_probs(const ph_c128* U, int32_t m, int64_t ldu, const int32_t* in_modes, int32_t n,
                               const int32_t* patterns, int64_t n_patterns, double* probs, const ph_opts* opt,
                               void* stream) {
@@ -728,10 +758,39 @@ extern "C" int ph_boson_probs_grad(const ph_c128* U, int32_t m, int64_t ldu, con
   if ((rc = check_boson_args(U, m, ldu, in_modes, n, patterns, n_patterns, PH_NMAX_GRAD))) return rc;
   if (n < 1) return fail(PH_EINVAL, "n=%d < 1", n);
   if (!dU) return fail(PH_EINVAL, "dU is NULL");
-  if (lddu < n) return fail(PH_EINVAL, "lddu=%lld < n=%d", (long long)lddu, n);
+  const int64_t need_ld = o.du_full ? m : n;
+  if (lddu < need_ld) return fail(PH_EINVAL, "lddu=%lld < %lld", (long long)lddu, (long long)need_ld);
   const int cus = num_cus();
   if (cus <= 0) return PH_EUNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
+  if (o.du_full) {
+    // per-photon columns into a workspace of their own, then folded onto the
+    // columns of U in a fixed order
+    void* ws = nullptr;
+    if ((rc = workspace_slot(st, (size_t)m * n * sizeof(double2), WS_BOSON_FOLD, &ws))) return rc;
+    Opts on = o;
+    on.du_full = false;
+    rc = boson_probs_grad_cols(st, U, m, ldu, in_modes, n, patterns, n_patterns, weights, probs,
+                               static_cast<ph_c128*>(ws), n, on, cus);
+    if (rc) return rc;
+    InModes im{};
+    for (int k = 0; k < n; ++k) im.v[k] = in_modes[k];
+    const int64_t tot = (int64_t)m * m;
+    hipLaunchKernelGGL(k_boson_fold_photons, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                       static_cast<const double2*>(ws), n, im, m, reinterpret_cast<double2*>(dU), lddu);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? PH_OK : hip_fail(e, "boson fold launch");
+  }
+  return boson_probs_grad_cols(st, U, m, ldu, in_modes, n, patterns, n_patterns, weights, probs, dU, lddu, o, cus);
+}
+
+namespace ph {
+
+// dU (m x n, row stride lddu): one column per input photon.
+static int boson_probs_grad_cols(hipStream_t st, const ph_c128* U, int32_t m, int64_t ldu, const int32_t* in_modes,
+                                 int32_t n, const int32_t* patterns, int64_t n_patterns, const double* weights,
+                                 double* probs, ph_c128* dU, int64_t lddu, const Opts& o, int cus) {
+  int rc;
   if (n >= GROUP_MIN_SINGLES + 1 && n_patterns > 0)
     return boson_grad_grouped(st, U, m, ldu, in_modes, n, patterns, n_patterns, weights, probs, dU, lddu, o, cus);
   BosonBufs b;
@@ -749,3 +808,5 @@ extern "C" int ph_boson_probs_grad(const ph_c128* U, int32_t m, int64_t ldu, con
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? PH_OK : hip_fail(e, "boson grad launch");
 }
+
+}  // namespace ph

@@ -30,14 +30,18 @@
 //     and written by one fixed lane only, so program order is the only
 //     ordering needed.
 //
-// The loop takes the terms in pairs (t, t+1), t even, with one copy of the
-// code for each: the step into t+1 always flips Gray bit 0, and the step into
-// t flips bit ctz(t), the same on every lane, so the choice between a
-// register-held column and a boundary column is a scalar branch taken once
-// per pair.
+// The loop takes the terms in blocks of 2^K: inside a block the steps flip
+// Gray bits 0..K-1 in a fixed pattern, so the stored-column updates, the
+// signs and the column addresses are compile-time constants (straight-line
+// code, no branch); the step into a block flips bit K + ctz(block index), the
+// same on every lane, and only that step branches (on the scalar bit index)
+// between a register-held group sum and one added to memory.
 //
-// The forward permanent comes out of the same sweep (prod of all rows).
-// All sums are in a fixed order, so results are bitwise reproducible.
+// The permanent itself is the expansion of the same sweep along row 0:
+// Eq. (S2) is linear in each row, so sum_delta (prod delta) prod_i r_i =
+// sum_j a_0j Mhat_0j with Mhat the sweep's unscaled sums; the finalize forms
+// it from the table's row 0 and M's row 0 in double-double.  All sums are in
+// a fixed order, so results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -129,7 +133,7 @@ __device__ __forceinline__ double reduce_scatter(double (&v)[CMAX]) {
 // Stored columns (K) and target wavefronts per SIMD per (rows per lane M,
 // lanes per term H).
 #ifndef PH_GRAD_K
-#define PH_GRAD_K(M, H) ((H) == 8 ? 4 : ((M) == 1 ? 1 : ((M) <= 4 ? 2 : 3)))
+#define PH_GRAD_K(M, H) ((H) == 8 ? 4 : ((M) == 1 ? 1 : ((M) <= 4 ? 2 : 4)))
 #endif
 #ifndef PH_GRAD_WAVES
 #define PH_GRAD_WAVES(M, H) ((H) == 8 ? ((M) <= 2 ? 3 : 2) : ((M) <= 1 ? 4 : ((M) <= 3 ? 3 : 2)))
@@ -145,17 +149,11 @@ __device__ __forceinline__ double reduce_scatter(double (&v)[CMAX]) {
 #ifndef PH_GRAD_H4_M4
 #define PH_GRAD_H4_M4 0
 #endif
-
-// stored columns kept in registers (default: all K)
+// stored columns whose entries each lane also keeps in registers (the
+// others are read from LDS when they flip)
 #ifndef PH_GRAD_KR
-#define PH_GRAD_KR(M, H) ((H) == 8 ? ((M) >= 3 ? 3 : 8) : ((M) == 5 ? 2 : 8))
+#define PH_GRAD_KR(M, H) ((M) <= 2 ? 4 : ((M) == 3 ? 2 : 1))
 #endif
-// log2 of the terms per loop iteration (bits below it flip without a branch)
-#ifndef PH_GRAD_LOGP
-#define PH_GRAD_LOGP(M, H) ((M) == 3 && (H) == 8 ? 2 : 1)
-#endif
-// terms summed in plain binary64 before each double-double accumulation
-constexpr uint32_t GRAD_FLUSH = 16;
 
 template <int M, int H>
 struct GradShape {
@@ -166,12 +164,7 @@ struct GradShape {
   // their group sums in registers of the owning lane
   static constexpr int R = 4;
   static constexpr int WAVES = PH_GRAD_WAVES(M, H);
-  // terms per loop iteration: 2^LOGP (LOGP <= K)
-  static constexpr int LOGP = PH_GRAD_LOGP(M, H) < K ? PH_GRAD_LOGP(M, H) : K;
-  // stored columns also held in registers (the rest are read from LDS when
-  // they flip): at least the LOGP columns of the straight-line steps
-  static constexpr int KR0 = PH_GRAD_KR(M, H) < K ? PH_GRAD_KR(M, H) : K;
-  static constexpr int KR = KR0 > LOGP ? KR0 : LOGP;
+  static constexpr int KR = PH_GRAD_KR(M, H) < K ? PH_GRAD_KR(M, H) : K;
 };
 
 struct GradArgs {
@@ -183,8 +176,6 @@ struct GradArgs {
   int64_t units;        // batch * s_per
   uint32_t* counter;
   double2* ghat;        // per (unit, wave): n x ROWS complex
-  double4* fparts;      // per (unit, wave): forward partial (dd)
-  int plain;
 };
 
 template <int M, int H>
@@ -192,7 +183,7 @@ struct GradLane {
   double2 r[M];
   double2 W[M];
   double2 G[GradShape<M, H>::K][M];
-  double2 colK[GradShape<M, H>::KR][M];  // the lane's rows of columns 1..KR
+  double2 colK[GradShape<M, H>::KR > 0 ? GradShape<M, H>::KR : 1][M];  // the lane's rows of columns 1..KR
 };
 
 // Group sums: wt * W summed over the NG groups, for each lane position in the
@@ -239,34 +230,36 @@ __device__ __forceinline__ void group_sum_add(const double2 (&W)[M], double wt, 
 }
 
 // Product of the rows owned by the other H - 1 lanes of the group, from each
-// lane's product of its own rows.
-template <int H>
+// lane's product of its own rows; NEG returns its negative (the sign folds
+// into the last multiply).
+template <int H, bool NEG>
 __device__ __forceinline__ double2 others_product(double2 own) {
   const double2 p1 = dpp_mov<DPP_QUAD_XOR1>(own);  // partner lane
   const double2 pair = cmul(own, p1);
   const double2 pair2 = dpp_mov<DPP_QUAD_XOR2>(pair);  // the other pair of the quad
+  const double2 p1s = NEG ? make_double2(-p1.x, -p1.y) : p1;
   if constexpr (H == 4) {
-    return cmul(p1, pair2);
+    return cmul(p1s, pair2);
   } else {
     const double2 quad = cmul(pair, pair2);
     const double2 quad2 = dpp_mov<DPP_HALF_MIRROR>(quad);  // the other quad of the 8
-    return cmul(cmul(p1, pair2), quad2);
+    return cmul(cmul(p1s, pair2), quad2);
   }
 }
 
-// One term: W_i += st q_i for the lane's rows and the full product st P into
-// sb (st = the term's sign).  Suffix products of the own rows, the group
-// exchange for O, then a running prefix t_i = st O prod_{k<i} r_k with
-// q_i st = t_i suf_{i+1}, the last multiply fused into the W update.
-template <int M, int H>
-__device__ __forceinline__ void grad_term(GradLane<M, H>& L, double st, double2& sb) {
+// One term: W_i += st q_i for the lane's rows (st = the term's sign, NEG
+// when it is negative; with ACT, st also carries the group's 0/1 activity
+// `act`).  Suffix products of the own rows, the group exchange for O, then a
+// running prefix t_i = st O prod_{k<i} r_k with q_i st = t_i suf_{i+1}, the
+// last multiply fused into the W update.
+template <int M, int H, bool NEG, bool ACT>
+__device__ __forceinline__ void grad_term(GradLane<M, H>& L, double act) {
   double2 suf[M];
   suf[M - 1] = L.r[M - 1];
 #pragma unroll
   for (int ii = M - 2; ii >= 0; --ii) suf[ii] = cmul(L.r[ii], suf[ii + 1]);
-  const double2 o = others_product<H>(suf[0]);
-  const double2 os = make_double2(st * o.x, st * o.y);
-  double2 t = os;
+  double2 t = others_product<H, NEG>(suf[0]);
+  if constexpr (ACT) t = make_double2(act * t.x, act * t.y);
 #pragma unroll
   for (int ii = 0; ii < M; ++ii) {
     if (ii < M - 1) {
@@ -281,11 +274,20 @@ __device__ __forceinline__ void grad_term(GradLane<M, H>& L, double st, double2&
       L.W[ii].y += t.y;
     }
   }
-  // full product st * O * P_own
-  sb.x = fma(os.x, suf[0].x, sb.x);
-  sb.x = fma(-os.y, suf[0].y, sb.x);
-  sb.y = fma(os.x, suf[0].y, sb.y);
-  sb.y = fma(os.y, suf[0].x, sb.y);
+}
+
+// f(integral_constant<B>) for the one B in [B0, E) equal to b (b must be in
+// range), as an if-else chain on the scalar b
+template <int B0, int E, typename F>
+__device__ __forceinline__ void select_case(int b, F&& f) {
+  if constexpr (B0 + 1 >= E) {
+    f(std::integral_constant<int, B0>{});
+  } else {
+    if (b == B0)
+      f(std::integral_constant<int, B0>{});
+    else
+      select_case<B0 + 1, E>(b, f);
+  }
 }
 
 // r += s * v (own rows, values already in registers)
@@ -309,7 +311,21 @@ __device__ __forceinline__ void grad_update(GradLane<M, H>& L, double s, const d
   }
 }
 
+// G_b += w * W (summation by parts of a stored column)
 template <int M, int H>
+__device__ __forceinline__ void stored_add(double2 (&G)[M], double w, const double2 (&W)[M]) {
+#pragma unroll
+  for (int ii = 0; ii < M; ++ii) {
+    G[ii].x = fma(w, W[ii].x, G[ii].x);
+    G[ii].y = fma(w, W[ii].y, G[ii].y);
+  }
+}
+
+// ACT: some term groups of the launch walk past the last chunk (orders with
+// fewer chunks than groups in a super-chunk); they run a copy of the sweep
+// with every term scaled by 0.  Without ACT every group is active and the
+// terms' signs are compile-time constants.
+template <int M, int H, bool ACT>
 __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs a) {
   using GS = GradShape<M, H>;
   constexpr int K = GS::K, ROWS = GS::ROWS, NG = GS::NG;
@@ -344,7 +360,6 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
         L.G[b][ii] = make_double2(0.0, 0.0);
         if (b < GS::KR) L.colK[b < GS::KR ? b : 0][ii] = tab[(b + 1) * ROWS + row0 + ii];
       }
-    dd2 acc = {0.0, 0.0, 0.0, 0.0};
     double bacc[GS::R];
 #pragma unroll
     for (int q = 0; q < GS::R; ++q) bacc[q] = 0.0;
@@ -354,7 +369,7 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
       const uint64_t chunk = (uint64_t)sc * NG + grp;
       const uint64_t k0 = chunk << c;
       // groups past the last chunk (tiny n) walk a copy but add nothing
-      const double act = chunk < nchunks ? 1.0 : 0.0;
+      const double act = (!ACT || chunk < nchunks) ? 1.0 : 0.0;
       // seed own rows: r_i = a_i0 + sum_{j>=1} delta_j a_ij (delta_j a_ij = (-delta_j/2) T[j])
       const uint64_t g0 = k0 ^ (k0 >> 1);
 #pragma unroll
@@ -366,70 +381,54 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
         if (row0 + ii >= n) L.r[ii] = make_double2(1.0, 0.0);  // padding rows
         L.W[ii] = make_double2(0.0, 0.0);
       }
-      double2 sb = make_double2(0.0, 0.0);
       // The step to offset t flips Gray bit b = ctz(t); its new value is set
-      // iff bit b+1 of k = k0 + t is clear: from t for b+1 < c, from the
-      // chunk parity at t = L/2.
-      const double sg_half = ((k0 >> c) & 1) ? -1.0 : 1.0;
-      const uint32_t len = 1u << c;
-      // Terms in runs of P = 2^LOGP: the steps inside a run flip bits below
-      // LOGP (straight-line code, columns in registers); the step into the
-      // run's first term flips bit ctz(t) >= LOGP.
-      constexpr int LOGP = GS::LOGP;
-      constexpr uint32_t P = 1u << LOGP;
-      for (uint32_t t = 0; t < len; t += P) {
-        if (t != 0) {
-          const int b = __builtin_ctz(t);
-          const double sgu = (b + 1 < c) ? (((t >> (b + 1)) & 1) ? -1.0 : 1.0) : sg_half;
-          if (b < K) {
-            static_for<LOGP, K>([&](auto bc) {
-              constexpr int bb = decltype(bc)::value;
-              if (b == bb) {
-                asm volatile("; stored column %0" ::"n"(bb));
-#pragma unroll
-                for (int ii = 0; ii < M; ++ii) {
-                  L.G[bb][ii].x = fma(2.0 * sgu, L.W[ii].x, L.G[bb][ii].x);
-                  L.G[bb][ii].y = fma(2.0 * sgu, L.W[ii].y, L.G[bb][ii].y);
-                }
-                if constexpr (bb < GS::KR)
-                  grad_apply<M, H>(L, sgu, L.colK[bb]);
-                else
-                  grad_update<M, H>(L, sgu, tab + (bb + 1) * ROWS + row0);
-              }
+      // iff bit b+1 of k = k0 + t is clear (k0 is a multiple of 2^c, so below
+      // bit c that is bit b+1 of t, and bit c is the chunk's parity).
+      //
+      // Terms in blocks of 2^K: inside a block the steps flip Gray bits
+      // 0..K-1 in a fixed pattern, so every stored-column update, sign and
+      // column address is a compile-time constant (the columns of bits below
+      // KR from registers, the others from LDS); only the step into a block
+      // flips a bit >= K, chosen at run time.
+      constexpr int NBK = 1 << K;
+      const uint32_t nblk = 1u << (c - K);
+      for (uint32_t m = 0; m < nblk; ++m) {
+        const uint32_t tb = m << K;
+        if (m != 0) {
+          // step into the block: bit b = K + ctz(m) of column b + 1;
+          // summation by parts adds -2 delta(t) W(t-1), delta(t) = -sgu
+          const int bq = __builtin_ctz(m);
+          const int b = K + bq;
+          const double sgu = (((k0 + tb) >> (b + 1)) & 1) ? -1.0 : 1.0;
+          if (bq < GS::R) {
+            const double qs = group_sum<M, H>(L.W, 2.0 * sgu);
+            // (the marker after the update keeps the cases apart)
+            select_case<0, GS::R>(bq, [&](auto qc) {
+              constexpr int q = decltype(qc)::value;
+              bacc[q] += qs;
+              asm volatile("; boundary column %0" ::"n"(q));
             });
           } else {
-            if (b < K + GS::R) {
-              const double qs = group_sum<M, H>(L.W, 2.0 * sgu);
-              static_for<0, GS::R>([&](auto qc) {
-                constexpr int q = decltype(qc)::value;
-                if (b == K + q) {
-                  asm volatile("; boundary column %0" ::"n"(q));
-                  bacc[q] += qs;
-                }
-              });
-            } else {
-              group_sum_add<M, H>(L.W, 2.0 * sgu, ghat + (size_t)(b + 1) * 2 * ROWS, gidx);
-            }
-            grad_update<M, H>(L, sgu, tab + (b + 1) * ROWS + row0);
+            group_sum_add<M, H>(L.W, 2.0 * sgu, ghat + (size_t)(b + 1) * 2 * ROWS, gidx);
           }
+          grad_update<M, H>(L, sgu, tab + (b + 1) * ROWS + row0);
         }
-        // the new value of bit LOGP-1 within the run comes from bit LOGP of t
-        const double sg_top = LOGP < c ? (((t >> LOGP) & 1) ? -1.0 : 1.0) : sg_half;
-        static_for<0, P>([&](auto sc) {
-          constexpr uint32_t so = decltype(sc)::value;
+        // the new value of bit K-1 (step 2^(K-1) of the block) comes from bit
+        // K of k
+        const double sg_top = (((k0 + tb) >> K) & 1) ? -1.0 : 1.0;
+        static_for<0, NBK>([&](auto sc) {
+          constexpr int so = decltype(sc)::value;
           if constexpr (so != 0) {
             constexpr int bb = __builtin_ctz(so);
-            const double sgu = bb + 1 < LOGP ? (((so >> (bb + 1)) & 1) ? -1.0 : 1.0) : sg_top;
-#pragma unroll
-            for (int ii = 0; ii < M; ++ii) {
-              L.G[bb][ii].x = fma(2.0 * sgu, L.W[ii].x, L.G[bb][ii].x);
-              L.G[bb][ii].y = fma(2.0 * sgu, L.W[ii].y, L.G[bb][ii].y);
-            }
-            grad_apply<M, H>(L, sgu, L.colK[bb]);
+            const double sgu = bb + 1 < K ? (((so >> (bb + 1)) & 1) ? -1.0 : 1.0) : sg_top;
+            stored_add<M, H>(L.G[bb], 2.0 * sgu, L.W);
+            if constexpr (bb < GS::KR)
+              grad_apply<M, H>(L, sgu, L.colK[bb]);
+            else
+              grad_update<M, H>(L, sgu, tab + (bb + 1) * ROWS + row0);
           }
-          grad_term<M, H>(L, (so & 1) ? -act : act, sb);
+          grad_term<M, H, (so & 1) != 0, ACT>(L, act);
         });
-        if (((t + P) & (GRAD_FLUSH - 1)) == 0 || t + P == len) flush(acc, sb, a.plain != 0, sig == 0);
       }
       // boundary terms delta_j(last) W(last) for every column
       const uint64_t kl = k0 + ((uint64_t)1 << c) - 1;
@@ -439,14 +438,7 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
       for (int j = K + 1; j < nc; ++j)
         group_sum_add<M, H>(L.W, ((gl >> (j - 1)) & 1) ? -1.0 : 1.0, ghat + (size_t)j * 2 * ROWS, gidx);
 #pragma unroll
-      for (int b = 0; b < K; ++b) {
-        const double dl = ((gl >> b) & 1) ? -1.0 : 1.0;
-#pragma unroll
-        for (int ii = 0; ii < M; ++ii) {
-          L.G[b][ii].x = fma(dl, L.W[ii].x, L.G[b][ii].x);
-          L.G[b][ii].y = fma(dl, L.W[ii].y, L.G[b][ii].y);
-        }
-      }
+      for (int b = 0; b < K; ++b) stored_add<M, H>(L.G[b], ((gl >> b) & 1) ? -1.0 : 1.0, L.W);
     }
     // register-held boundary columns and stored columns into the accumulator
     if (out_lane) {
@@ -457,9 +449,6 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
 #pragma unroll
     for (int b = 0; b < K; ++b)
       if (b + 1 < nc) group_sum_add<M, H>(L.G[b], 1.0, ghat + (size_t)(b + 1) * 2 * ROWS, gidx);
-    if (sig != 0) acc = dd2{0.0, 0.0, 0.0, 0.0};
-    acc = wave_reduce(acc, a.plain != 0);
-    if (lane == 0) a.fparts[slot] = make_double4(acc.hr, acc.lr, acc.hi, acc.li);
     __syncthreads();
   }
 }
@@ -481,12 +470,37 @@ __global__ void k_grad_prep(const double2* __restrict__ a, int n, int rows, doub
   }
 }
 
+// acc += a * m, a complex binary64, m a double-double per component: the
+// products of the high parts are split exactly (FMA), the rest added plainly.
+__device__ __forceinline__ void dd_cmul_acc(dd2& acc, double2 a, const dd2& m) {
+  double s, e;
+  const double p1 = a.x * m.hr, p2 = a.y * m.hi, p3 = a.x * m.hi, p4 = a.y * m.hr;
+  const double lo_r = fma(a.x, m.hr, -p1) - fma(a.y, m.hi, -p2) + (a.x * m.lr - a.y * m.li);
+  const double lo_i = fma(a.x, m.hi, -p3) + fma(a.y, m.hr, -p4) + (a.x * m.li + a.y * m.lr);
+  two_sum(acc.hr, p1, s, e);
+  acc.hr = s;
+  acc.lr += e;
+  two_sum(acc.hr, -p2, s, e);
+  acc.hr = s;
+  acc.lr += e + lo_r;
+  two_sum(acc.hi, p3, s, e);
+  acc.hi = s;
+  acc.li += e;
+  two_sum(acc.hi, p4, s, e);
+  acc.hi = s;
+  acc.li += e + lo_i;
+}
+
 // Per matrix: M = 2^-(n-1) sum over the (unit, wave) accumulators in order
-// (n x ncols, row-major), grad = g * conj(M), perm = 2^-(n-1) sum of forward
-// partials.
-__global__ void k_grad_finalize(const double2* __restrict__ ghat, const double4* __restrict__ fparts, int n,
+// (n x ncols, row-major), grad = g * conj(M).  The permanent is the
+// expansion of the same sum along row 0: Eq. (S2)'s sum is linear in each
+// row, so sum_delta (prod delta) prod_i r_i = sum_j a_0j sum_delta
+// (prod delta) delta_j q_0 = sum_j a_0j Mhat_0j, Mhat the unscaled sums
+// (a_00 = T[0]_0, a_0j = -T[j]_0 / 2 from the table), added in j order.
+__global__ void k_grad_finalize(const double2* __restrict__ ghat, const double2* __restrict__ tabs, int n,
                                 int ncols, int rows, int s_per, int plain, const double2* __restrict__ gout,
                                 double2* __restrict__ pout, double2* __restrict__ grad) {
+  __shared__ dd2 row0[NMAX_GRAD];
   const int64_t mat = blockIdx.x;
   const int64_t slots = (int64_t)s_per * 4, first = mat * slots;
   const double2 g = gout ? gout[mat] : make_double2(1.0, 0.0);
@@ -502,24 +516,31 @@ __global__ void k_grad_finalize(const double2* __restrict__ ghat, const double4*
         dd_accumulate(s, v.x, v.y);
       }
     }
+    if (i == 0) row0[j] = s;
     const double mr = ldexp(s.hr, -(n - 1)) + ldexp(s.lr, -(n - 1));
     const double mi = ldexp(s.hi, -(n - 1)) + ldexp(s.li, -(n - 1));
     // g * conj(M)
     grad[mat * n * ncols + e] = make_double2(g.x * mr + g.y * mi, g.y * mr - g.x * mi);
   }
-  if (pout && threadIdx.x == 0) {
-    dd2 s = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t q = 0; q < slots; ++q) {
-      const double4 v = fparts[first + q];
-      if (plain) {
-        s.hr += v.x;
-        s.hi += v.z;
-      } else {
-        s = dd_add(s, dd2{v.x, v.y, v.z, v.w});
+  if (pout) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double2* t = tabs + (size_t)mat * ncols * rows;
+      dd2 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int j = 0; j < ncols; ++j) {
+        double2 a0 = t[(size_t)j * rows];
+        if (j >= 1) a0 = make_double2(-0.5 * a0.x, -0.5 * a0.y);  // exact
+        const dd2 m = row0[j];
+        if (plain) {
+          acc.hr += a0.x * m.hr - a0.y * m.hi;
+          acc.hi += a0.x * m.hi + a0.y * m.hr;
+        } else {
+          dd_cmul_acc(acc, a0, m);
+        }
       }
+      pout[mat] = make_double2(ldexp(acc.hr, -(n - 1)) + ldexp(acc.lr, -(n - 1)),
+                               ldexp(acc.hi, -(n - 1)) + ldexp(acc.li, -(n - 1)));
     }
-    pout[mat] = make_double2(ldexp(s.hr, -(n - 1)) + ldexp(s.lr, -(n - 1)),
-                             ldexp(s.hi, -(n - 1)) + ldexp(s.li, -(n - 1)));
   }
 }
 
@@ -535,15 +556,17 @@ __global__ void k_grad_n1(const double2* __restrict__ a, int64_t batch, const do
 
 __global__ void k_reset1(uint32_t* c) { *c = 0; }
 
-// Layout of one gradient sweep: lanes per term, rows per lane, its kernel.
+// Layout of one gradient sweep: lanes per term, rows per lane, its kernels
+// (every group active; some groups past the last chunk).
 struct GradLayout {
   int H, M, K;
   const void* kern;
+  const void* kern_act;
 };
 
 template <int M, int H>
 static GradLayout layout() {
-  return GradLayout{H, M, GradShape<M, H>::K, (const void*)&k_grad<M, H>};
+  return GradLayout{H, M, GradShape<M, H>::K, (const void*)&k_grad<M, H, false>, (const void*)&k_grad<M, H, true>};
 }
 
 static GradLayout grad_layout(int n) {
@@ -553,7 +576,7 @@ static GradLayout grad_layout(int n) {
       case 3: return layout<3, 8>();
       case 4: return layout<4, 8>();
     }
-    return GradLayout{0, 0, 0, nullptr};
+    return GradLayout{0, 0, 0, nullptr, nullptr};
   }
   switch ((n + 3) / 4) {
     case 1: return layout<1, 4>();
@@ -566,7 +589,7 @@ static GradLayout grad_layout(int n) {
 #endif
     case 5: return layout<5, 4>();
   }
-  return GradLayout{0, 0, 0, nullptr};
+  return GradLayout{0, 0, 0, nullptr, nullptr};
 }
 
 int grad_rows(int n) {
@@ -589,11 +612,15 @@ int grad_sweep(const double2* tabs, int n, int ncols, int64_t batch, const doubl
   // the four wavefronts of a unit (4 * ng chunks) where the sweep is long enough
   const int need = 2 + (ng == 8 ? 3 : 4);
   int c = o.chunk_log2 > 0 ? o.chunk_log2 : std::min(10, nb - need);
-  c = std::max(K, std::min(c, nb));  // K >= LOGP, so a chunk holds whole runs
-  const int64_t nsuper = (int64_t)((((uint64_t)1 << (nb - c)) + ng - 1) / ng);
+  c = std::max(K, std::min(c, nb));  // a chunk holds whole blocks of 2^K terms
+  const uint64_t nchunks = (uint64_t)1 << (nb - c);
+  const int64_t nsuper = (int64_t)((nchunks + ng - 1) / ng);
+  // a super-chunk holds ng chunks: groups past the last chunk need the kernel
+  // that scales their terms by 0
+  const void* kern = nchunks % ng == 0 ? lay.kern : lay.kern_act;
   const size_t lds = (size_t)ncols * rows * sizeof(double2);
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lay.kern, 256, lds);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds);
   if (e != hipSuccess) return hip_fail(e, "occupancy");
   per_cu = std::max(1, per_cu);
   if (o.waves > 0) per_cu = std::min(per_cu, o.waves);
@@ -604,8 +631,7 @@ int grad_sweep(const double2* tabs, int n, int ncols, int64_t batch, const doubl
   s_per = std::min<int64_t>(s_per, std::max<int64_t>(1, nsuper / 4));
   const int64_t units = batch * s_per;
   const size_t ghat_elems = (size_t)units * 4 * ncols * rows;
-  const size_t off_f = (((ghat_elems * sizeof(double2)) + 255) & ~(size_t)255);
-  const size_t off_c = off_f + (((size_t)units * 4 * sizeof(double4) + 255) & ~(size_t)255);
+  const size_t off_c = (((ghat_elems * sizeof(double2)) + 255) & ~(size_t)255);
   void* ws = nullptr;
   int rc = workspace(st, off_c + 256, &ws);
   if (rc) return rc;
@@ -620,15 +646,13 @@ int grad_sweep(const double2* tabs, int n, int ncols, int64_t batch, const doubl
   ga.units = units;
   ga.counter = reinterpret_cast<uint32_t*>(base + off_c);
   ga.ghat = reinterpret_cast<double2*>(base);
-  ga.fparts = reinterpret_cast<double4*>(base + off_f);
-  ga.plain = o.plain ? 1 : 0;
   hipLaunchKernelGGL(k_reset1, dim3(1), dim3(1), 0, st, ga.counter);
   const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(blocks_full, units));
   void* args[] = {&ga};
-  e = hipLaunchKernel(lay.kern, dim3((unsigned)grid), dim3(256), args, lds, st);
+  e = hipLaunchKernel(kern, dim3((unsigned)grid), dim3(256), args, lds, st);
   if (e != hipSuccess) return hip_fail(e, "grad sweep launch");
-  hipLaunchKernelGGL(k_grad_finalize, dim3((unsigned)batch), dim3(256), 0, st, ga.ghat, ga.fparts, n, ncols, rows,
-                     (int)s_per, ga.plain, gout, pout, grad);
+  hipLaunchKernelGGL(k_grad_finalize, dim3((unsigned)batch), dim3(256), 0, st, ga.ghat, tabs, n, ncols, rows,
+                     (int)s_per, o.plain ? 1 : 0, gout, pout, grad);
   e = hipGetLastError();
   return e == hipSuccess ? PH_OK : hip_fail(e, "grad launch");
 }
@@ -645,9 +669,9 @@ int perm_grad_launch(const double2* A, int n, int64_t batch, const double2* gout
   }
   const int rows = grad_rows(n);
   if (rows <= 0) return fail(PH_ERANGE, "no gradient kernel for n=%d", n);
-  // the tables in a workspace slot of their own: the sweep may grow slot 0
+  // the tables in a workspace slot of their own: the sweep may grow WS_SWEEP
   void* tw = nullptr;
-  int rc = workspace_slot(st, (size_t)batch * n * rows * sizeof(double2), 3, &tw);
+  int rc = workspace_slot(st, (size_t)batch * n * rows * sizeof(double2), WS_GRAD_TABLES, &tw);
   if (rc) return rc;
   double2* tabs = static_cast<double2*>(tw);
   hipLaunchKernelGGL(k_grad_prep, dim3((unsigned)batch), dim3(256), 0, st, A, n, rows, tabs);

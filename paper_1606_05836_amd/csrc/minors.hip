@@ -212,7 +212,7 @@ int row_minors_launch(const double2* tabs, int n_rows, int64_t batch, double2* o
   bpm = std::min<int64_t>(bpm, std::max<int64_t>(1, (int64_t)((nsuper + 3) / 4)));
   const int nc = n_rows + 1;
   void* ws = nullptr;
-  int rc = workspace_slot(st, (size_t)batch * bpm * nc * sizeof(double4), 5, &ws);
+  int rc = workspace_slot(st, (size_t)batch * bpm * nc * sizeof(double4), WS_MINORS, &ws);
   if (rc) return rc;
   double4* parts = static_cast<double4*>(ws);
   int b = (int)bpm;
@@ -293,14 +293,14 @@ extern "C" int ph_perm_row_minors(const ph_c128* B, int32_t n, int64_t batch, ph
     hipLaunchKernelGGL(k_fill_one, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, st, out, batch);
   } else if (n >= MINORS_NMIN) {
     void* ws = nullptr;
-    if ((rc = workspace_slot(st, (size_t)batch * n * nc * sizeof(double2), 6, &ws))) return rc;
+    if ((rc = workspace_slot(st, (size_t)batch * n * nc * sizeof(double2), WS_MINORS_TABLES, &ws))) return rc;
     double2* tabs = static_cast<double2*>(ws);
     hipLaunchKernelGGL(k_minors_prep, dim3((unsigned)batch), dim3(256), 0, st, b, n, tabs);
     if ((rc = row_minors_launch(tabs, n, batch, out, st, cus))) return rc;
   } else {
     void* ws = nullptr;
     const size_t sq = (size_t)batch * nc * nc * sizeof(double2);
-    if ((rc = workspace_slot(st, 2 * sq, 6, &ws))) return rc;
+    if ((rc = workspace_slot(st, 2 * sq, WS_MINORS_TABLES, &ws))) return rc;
     double2* sqm = static_cast<double2*>(ws);
     double2* grad = reinterpret_cast<double2*>(static_cast<char*>(ws) + sq);
     hipLaunchKernelGGL(k_minors_square, dim3((unsigned)batch), dim3(256), 0, st, b, n, sqm);

@@ -87,9 +87,9 @@ static std::map<std::tuple<int, hipStream_t, int>, Buf> g_ws;
 
 // Library-owned scratch for one (device, stream, slot); grown on demand.
 // Work on one stream is ordered, so reuse across calls on that stream is
-// safe.  Slot 0 belongs to the permanent kernels; a caller that composes them
-// keeps its own buffers in another slot.
-int workspace_slot(hipStream_t st, size_t bytes, int slot, void** out) {
+// safe.  The slots (WsSlot, ph_host.hpp) separate the callers' buffers.
+int workspace_slot(hipStream_t st, size_t bytes, int slot, void** out, bool* fresh) {
+  if (fresh) *fresh = false;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -108,12 +108,13 @@ int workspace_slot(hipStream_t st, size_t bytes, int slot, void** out) {
     e = hipMalloc(&b.p, cap);
     if (e != hipSuccess) return fail(PH_ENOMEM, "hipMalloc(%zu): %s", cap, hipGetErrorString(e));
     b.cap = cap;
+    if (fresh) *fresh = true;
   }
   *out = b.p;
   return PH_OK;
 }
 
-int workspace(hipStream_t st, size_t bytes, void** out) { return workspace_slot(st, bytes, 0, out); }
+int workspace(hipStream_t st, size_t bytes, void** out) { return workspace_slot(st, bytes, WS_SWEEP, out); }
 
 // ------------------------------------------------------------------ options
 
@@ -130,14 +131,18 @@ int read_opts(const ph_opts* o, Opts* r) {
   if (o) {
     if (o->algo != PH_GLYNN && o->algo != PH_RYSER) return fail(PH_EINVAL, "opts.algo=%d", o->algo);
     if (o->accum != PH_ACC_DD && o->accum != PH_ACC_PLAIN) return fail(PH_EINVAL, "opts.accum=%d", o->accum);
-    if (o->chunk_log2 < 0 || o->chunk_log2 > 62) return fail(PH_EINVAL, "opts.chunk_log2=%d", o->chunk_log2);
+    if (o->chunk_log2 < 0) return fail(PH_EINVAL, "opts.chunk_log2=%d < 0", o->chunk_log2);
     if (o->waves < 0 || o->waves > 8) return fail(PH_EINVAL, "opts.waves=%d", o->waves);
-    if ((o->flags & ~(PH_FLAG_UNGROUPED | PH_FLAG_UNSORTED)) != 0) return fail(PH_EINVAL, "opts.flags=%u", o->flags);
+    if ((o->flags & ~(PH_FLAG_UNGROUPED | PH_FLAG_UNSORTED | PH_FLAG_DU_FULL)) != 0)
+      return fail(PH_EINVAL, "opts.flags=%u", o->flags);
     d.ungrouped = (o->flags & PH_FLAG_UNGROUPED) != 0;
     d.unsorted = (o->flags & PH_FLAG_UNSORTED) != 0;
+    d.du_full = (o->flags & PH_FLAG_DU_FULL) != 0;
     d.algo = o->algo;
     d.plain = o->accum == PH_ACC_PLAIN;
-    d.chunk_log2 = o->chunk_log2;
+    // longer chunks are clamped: the sweeps count steps inside a chunk in
+    // 32-bit integers, and the row-sum drift grows with the chunk length
+    d.chunk_log2 = std::min<int32_t>(o->chunk_log2, PH_CHUNK_LOG2_MAX);
     d.waves = o->waves;
   }
   *r = d;
@@ -189,40 +194,38 @@ extern "C" int ph_perm(const ph_c128* A, int32_t n, int64_t lda, ph_c128* out, c
 
 namespace ph {
 
-// Sweep the chunks [chunk0, chunk0 + nchunks) of length 2^c of one matrix:
-// every workgroup builds the table from A in its LDS, and one partial per wave
-// is written to the workspace; *parts and *nparts describe them.
-static int sweep_share(const double2* A, int n, int64_t lda, int c, uint64_t chunk0, uint64_t nchunks,
-                       const Opts& o, hipStream_t st, int cus, double4** parts, int64_t* nparts) {
-  hipError_t e;
+// Launch shape of the one-matrix sweep over `nchunks` chunks: 256-thread
+// workgroups, as many as can be resident (or as waves per SIMD asks), at most
+// one per four super-chunks.
+int single_geometry(int n, const Opts& o, int cus, uint64_t nchunks, SweepGeom* g) {
   const uint64_t nsuper = (nchunks + 63) / 64;
-  const void* kern = single_kernel(n, o.algo);
-  if (!kern) return fail(PH_ERANGE, "no kernel for n=%d", n);
-  const size_t lds = single_lds_bytes(n);
+  g->kern = single_kernel(n, o.algo);
+  if (!g->kern) return fail(PH_ERANGE, "no kernel for n=%d", n);
+  g->lds = single_lds_bytes(n);
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, g->kern, 256, g->lds);
   if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
   if (per_cu < 1) return fail(PH_EHIP, "kernel for n=%d cannot be resident", n);
   if (o.waves > 0) per_cu = std::min(per_cu, o.waves);
   uint64_t blocks = (uint64_t)cus * per_cu;
   blocks = std::min<uint64_t>(blocks, (nsuper + 3) / 4);
-  blocks = std::max<uint64_t>(blocks, 1);
-  const uint64_t nwaves = blocks * 4;
-  void* ws = nullptr;
-  int rc = workspace(st, nwaves * sizeof(double4), &ws);
-  if (rc) return rc;
-  double4* pw = reinterpret_cast<double4*>(ws);
+  g->blocks = std::max<uint64_t>(blocks, 1);
+  return PH_OK;
+}
+
+// Enqueue the sweep of the chunks [chunk0, chunk0 + nchunks) of length 2^c
+// of one matrix: every workgroup builds the table from A in its LDS and each
+// wave writes one partial to parts (4 * blocks of them).
+int launch_single(const SweepGeom& g, const double2* A, int64_t lda, int c, uint64_t chunk0, uint64_t nchunks,
+                  int plain, double4* parts, hipStream_t st) {
   const double2* a = A;
   int64_t ld = lda;
   int cc = c;
   uint64_t ch0 = chunk0, nch = nchunks;
-  int plain = o.plain ? 1 : 0;
-  void* args[] = {&a, &ld, &cc, &ch0, &nch, &pw, &plain};
-  e = hipLaunchKernel(kern, dim3((unsigned)blocks), dim3(256), args, lds, st);
-  if (e != hipSuccess) return hip_fail(e, "sweep launch");
-  *parts = pw;
-  *nparts = (int64_t)nwaves;
-  return PH_OK;
+  int pl = plain;
+  void* args[] = {&a, &ld, &cc, &ch0, &nch, &parts, &pl};
+  const hipError_t e = hipLaunchKernel(g.kern, dim3((unsigned)g.blocks), dim3(256), args, g.lds, st);
+  return e == hipSuccess ? PH_OK : hip_fail(e, "sweep launch");
 }
 
 int perm_single(const double2* A, int n, int64_t lda, double2* out, const Opts& o, hipStream_t st, int cus) {
@@ -234,14 +237,17 @@ int perm_single(const double2* A, int n, int64_t lda, double2* out, const Opts& 
   }
   const int nb = gray_bits(n, o.algo);
   const int c = pick_chunk_log2(n, o.algo, o.chunk_log2);
-  double4* parts = nullptr;
-  int64_t nparts = 0;
-  int rc = sweep_share(A, n, lda, c, 0, (uint64_t)1 << (nb - c), o, st, cus, &parts, &nparts);
+  const uint64_t nchunks = (uint64_t)1 << (nb - c);
+  SweepGeom g;
+  int rc = single_geometry(n, o, cus, nchunks, &g);
   if (rc) return rc;
-  launch_finalize_single(parts, nparts, n, o.algo, o.plain, out, st);
+  void* ws = nullptr;
+  if ((rc = workspace(st, g.blocks * 4 * sizeof(double4), &ws))) return rc;
+  double4* parts = static_cast<double4*>(ws);
+  if ((rc = launch_single(g, A, lda, c, 0, nchunks, o.plain ? 1 : 0, parts, st))) return rc;
+  launch_finalize_single(parts, (int64_t)g.blocks * 4, n, o.algo, o.plain, out, st);
   e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(e, "kernel launch");
-  return PH_OK;
+  return e == hipSuccess ? PH_OK : hip_fail(e, "finalize launch");
 }
 
 }  // namespace ph
@@ -285,8 +291,15 @@ extern "C" int ph_perm_partial(const ph_c128* A, int32_t n, int64_t lda, uint64_
   double4* parts = nullptr;
   int64_t nparts = 0;
   if (k_end > k_begin) {
-    rc = sweep_share(reinterpret_cast<const double2*>(A), n, lda, c, k_begin >> c, (k_end - k_begin) >> c, o, st,
-                     di.cus, &parts, &nparts);
+    const uint64_t nchunks = (k_end - k_begin) >> c;
+    SweepGeom g;
+    if ((rc = single_geometry(n, o, di.cus, nchunks, &g))) return rc;
+    void* ws = nullptr;
+    if ((rc = workspace(st, g.blocks * 4 * sizeof(double4), &ws))) return rc;
+    parts = static_cast<double4*>(ws);
+    nparts = (int64_t)g.blocks * 4;
+    rc = launch_single(g, reinterpret_cast<const double2*>(A), lda, c, k_begin >> c, nchunks, o.plain ? 1 : 0, parts,
+                       st);
     if (rc) return rc;
   }
   launch_reduce_partials(parts, nparts, o.plain ? 1 : 0, out, st);  // zero for an empty range

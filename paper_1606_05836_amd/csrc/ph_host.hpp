@@ -17,18 +17,44 @@ struct Opts {
   int waves = 0;       // waves per SIMD, 0 = occupancy limit
   bool ungrouped = false;  // boson probabilities: no multiplicity grouping
   bool unsorted = false;   // boson samples: placement order
+  bool du_full = false;    // boson gradient: m x m dU, photons folded onto U's columns
 };
 
 int fail(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 int read_opts(const ph_opts* o, Opts* r);
 int workspace(hipStream_t st, size_t bytes, void** out);
-int workspace_slot(hipStream_t st, size_t bytes, int slot, void** out);
+// Workspace slots: each call keeps its buffers in its own slot, so that a
+// call composed of others (the boson layer over the gradient sweep, the
+// sampler over the row minors) never has a buffer it still needs grown
+// (reallocated) under it.
+enum WsSlot {
+  WS_SWEEP = 0,          // partial sums of the one-matrix and gradient sweeps
+  WS_BOSON = 1,          // ungrouped boson layer
+  WS_BOSON_GROUPED = 2,  // multiplicity-grouped boson layer
+  WS_GRAD_TABLES = 3,    // gradient-sweep tables
+  WS_SAMPLER = 4,        // sampler state
+  WS_MINORS = 5,         // row-minor partial sums
+  WS_MINORS_TABLES = 6,  // row-minor tables
+  WS_BOSON_FOLD = 7      // per-photon boson gradient before the fold onto U's columns
+};
+// fresh (nullable) tells whether the buffer was (re)allocated by this call
+int workspace_slot(hipStream_t st, size_t bytes, int slot, void** out, bool* fresh = nullptr);
 int num_cus();
 int gray_bits(int n, int algo);
 int min_chunk_log2(int nb);
 int pick_chunk_log2(int n, int algo, int requested);
 int perm_single(const double2* A, int n, int64_t lda, double2* out, const Opts& o, hipStream_t st, int cus);
+
+// One-matrix sweep launches (permhip.cpp).
+struct SweepGeom {
+  const void* kern = nullptr;
+  size_t lds = 0;
+  uint64_t blocks = 0;  // workgroups of 256 threads; 4 partials each
+};
+int single_geometry(int n, const Opts& o, int cus, uint64_t nchunks, SweepGeom* g);
+int launch_single(const SweepGeom& g, const double2* A, int64_t lda, int c, uint64_t chunk0, uint64_t nchunks,
+                  int plain, double4* parts, hipStream_t st);
 
 // rocTX range for the lifetime of the object when PERMHIP_ROCTX=1 (trace.cpp).
 struct TraceRange {

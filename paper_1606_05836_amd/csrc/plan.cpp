@@ -58,11 +58,18 @@ struct PlanImpl {
   void* last_out = nullptr;
   hipStream_t last_stream = nullptr;
   bool launched = false;
+  // recorded after every execution: a replay on another stream first waits
+  // for it, since the graph's counters and partials are the plan's own
+  hipEvent_t done = nullptr;
   // matrices of order >= SOLO_NMIN (and no caller-built tables) go through
   // the one-matrix sweep after the graph, which splits each term over two
   // lanes; the graph's finalize writes a placeholder that this overwrites
   std::vector<int64_t> solo;
   Opts opts;
+  // waves per SIMD of each size bucket's sweep (0: as many as fit), and the
+  // (chunk log2, waves) chosen per order
+  int bucket_waves[NBUCKETS] = {};
+  std::map<int, std::pair<int, int>> shape;
 };
 
 constexpr int SOLO_NMIN = 45;
@@ -87,7 +94,10 @@ static void seal_args(KernelNode& k, const std::vector<size_t>& sizes) {
 
 static void destroy_impl(PlanImpl* p) {
   if (!p) return;
+  // each execution waited for the previous one, so the last stream's work
+  // is the last to touch the plan's memory
   if (p->launched) hipStreamSynchronize(p->last_stream);
+  if (p->done) hipEventDestroy(p->done);
   if (p->exec) hipGraphExecDestroy(p->exec);
   if (p->graph) hipGraphDestroy(p->graph);
   if (p->dmem) hipFree(p->dmem);
@@ -96,18 +106,28 @@ static void destroy_impl(PlanImpl* p) {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// ------------------------------------------------------------- chunk tuning
+// ------------------------------------------------------------- shape tuning
 
+#ifndef PH_BUILD_ID
+#define PH_BUILD_ID "unversioned"
+#endif
+
+// A tuned shape is valid for one build of the kernels (PH_BUILD_ID, a hash
+// of the kernel sources set by the build), one device kind and one order.
 struct TuneKey {
-  std::string arch;
+  std::string build, arch;
   int cus, n, algo, plain;
   bool operator<(const TuneKey& o) const {
-    return std::tie(arch, cus, n, algo, plain) < std::tie(o.arch, o.cus, o.n, o.algo, o.plain);
+    return std::tie(build, arch, cus, n, algo, plain) < std::tie(o.build, o.arch, o.cus, o.n, o.algo, o.plain);
   }
+};
+struct Shape {
+  int c = 0;      // log2 chunk length
+  int waves = 0;  // wavefronts per SIMD (workgroups of 4 waves per CU)
 };
 
 static std::mutex g_tune_mu;
-static std::map<TuneKey, int> g_tune;
+static std::map<TuneKey, Shape> g_tune;
 static bool g_tune_loaded = false;
 
 // Range of chunk lengths a plan may use for order n.  The upper bound is the
@@ -133,11 +153,25 @@ static int default_chunk(int n, int algo) {
   return std::max(lo, std::min(hi, 12));
 }
 
+// Workgroups per CU the batched sweep of order n can hold (its bucket's
+// kernel and LDS).
+static int bucket_occupancy(int n, int algo) {
+  const int bk = bucket_of(n);
+  if (bk < 0) return 1;
+  int per_cu = 0;
+  const size_t lds = (size_t)BUCKET_HI[bk] * BUCKET_HI[bk] * sizeof(double2);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel(bk, algo), 256, lds) != hipSuccess)
+    return 1;
+  return std::max(per_cu, 1);
+}
+
 static std::string cache_path() {
   const char* p = getenv("PERMHIP_TUNE_CACHE");
   return p ? std::string(p) : std::string();
 }
 
+// One entry per line: build arch cus n algo plain c waves.  Entries of other
+// builds are kept in the file but never used.
 static void load_cache_locked() {
   if (g_tune_loaded) return;
   g_tune_loaded = true;
@@ -145,12 +179,11 @@ static void load_cache_locked() {
   if (path.empty()) return;
   std::ifstream f(path);
   std::string line;
-  // one entry per line: arch cus n algo plain c
   while (std::getline(f, line)) {
     std::istringstream is(line);
     TuneKey k;
-    int c;
-    if (is >> k.arch >> k.cus >> k.n >> k.algo >> k.plain >> c) g_tune[k] = c;
+    Shape v;
+    if (is >> k.build >> k.arch >> k.cus >> k.n >> k.algo >> k.plain >> v.c >> v.waves) g_tune[k] = v;
   }
 }
 
@@ -159,8 +192,8 @@ static void save_cache_locked() {
   if (path.empty()) return;
   std::ofstream f(path, std::ios::trunc);
   for (auto& kv : g_tune)
-    f << kv.first.arch << ' ' << kv.first.cus << ' ' << kv.first.n << ' ' << kv.first.algo << ' ' << kv.first.plain
-      << ' ' << kv.second << '\n';
+    f << kv.first.build << ' ' << kv.first.arch << ' ' << kv.first.cus << ' ' << kv.first.n << ' ' << kv.first.algo
+      << ' ' << kv.first.plain << ' ' << kv.second.c << ' ' << kv.second.waves << '\n';
 }
 
 int plan_build(const int32_t* n_host, const int64_t* off_host, int64_t batch, const Opts& o, const int32_t* c_force,
@@ -169,27 +202,30 @@ int plan_build(const int32_t* n_host, const int64_t* off_host, int64_t batch, co
 // Terms one tuning run may sweep: candidates are timed on synthetic batches
 // of about this many terms.  Orders with more terms per matrix than this are
 // not timed (a run would be a whole permanent per candidate, seconds to
-// hours); they take the default length, whose seed work is well under 1% of
-// the sweep at that size.
+// hours); they take the default length and as many waves as fit, whose seed
+// work is well under 1% of the sweep at that size.
 constexpr int TUNE_LOG2_TERMS = 27;
 
-// Time the batched sweep for each candidate chunk length on a synthetic batch
-// of order-n matrices (about 2^27 terms) and keep the fastest.
-static int tune_chunk(int n, int algo, bool plain, hipStream_t st, int* c_out) {
+// Time the batched sweep for every (chunk length, waves per SIMD) candidate
+// on a synthetic batch of order-n matrices (about 2^27 terms) and keep the
+// fastest.
+static int tune_shape(int n, int algo, bool plain, hipStream_t st, Shape* out) {
   int lo, hi;
   chunk_range(n, algo, &lo, &hi);
   const int nb = gray_bits(n, algo);
-  if (lo == hi || nb > TUNE_LOG2_TERMS) {
-    *c_out = default_chunk(n, algo);
+  const int occ = bucket_occupancy(n, algo);
+  if (nb > TUNE_LOG2_TERMS || (lo == hi && occ == 1)) {
+    out->c = default_chunk(n, algo);
+    out->waves = 0;
     return PH_OK;
   }
   const int64_t copies = (int64_t)1 << std::min(TUNE_LOG2_TERMS - nb, 14);
   const int64_t elems = copies * n * n;
   double2* a = nullptr;
-  double2* out = nullptr;
+  double2* res = nullptr;
   hipError_t e = hipMalloc(&a, elems * sizeof(double2) + copies * sizeof(double2) + 256);
   if (e != hipSuccess) return fail(PH_ENOMEM, "tuning buffer: %s", hipGetErrorString(e));
-  out = a + elems;
+  res = a + elems;
   launch_fill_synthetic(a, elems, st);
   std::vector<int32_t> ns(copies, n), cs(copies);
   hipEvent_t e0, e1;
@@ -199,60 +235,65 @@ static int tune_chunk(int n, int algo, bool plain, hipStream_t st, int* c_out) {
   o.algo = algo;
   o.plain = plain;
   float best = 1e30f;
-  int best_c = default_chunk(n, algo);
+  Shape best_s{default_chunk(n, algo), 0};
   int rc = PH_OK;
   for (int c = lo; c <= hi && rc == PH_OK; ++c) {
-    std::fill(cs.begin(), cs.end(), c);
-    PlanImpl* p = nullptr;
-    rc = plan_build(ns.data(), nullptr, copies, o, cs.data(), st, &p);
-    if (rc) break;
-    float ms = 1e30f;
-    for (int rep = 0; rep < 2 && rc == PH_OK; ++rep) {
-      hipEventRecord(e0, st);
-      rc = plan_exec(p, a, out, st);
-      hipEventRecord(e1, st);
-      hipEventSynchronize(e1);
-      float t = 0;
-      hipEventElapsedTime(&t, e0, e1);
-      if (rep == 1) ms = t;
-    }
-    destroy_impl(p);
-    if (ms < best) {
-      best = ms;
-      best_c = c;
+    for (int w = 1; w <= occ && rc == PH_OK; ++w) {
+      std::fill(cs.begin(), cs.end(), c);
+      o.waves = w;
+      PlanImpl* p = nullptr;
+      rc = plan_build(ns.data(), nullptr, copies, o, cs.data(), st, &p);
+      if (rc) break;
+      float ms = 1e30f;
+      for (int rep = 0; rep < 2 && rc == PH_OK; ++rep) {
+        hipEventRecord(e0, st);
+        rc = plan_exec(p, a, res, st);
+        hipEventRecord(e1, st);
+        hipEventSynchronize(e1);
+        float t = 0;
+        hipEventElapsedTime(&t, e0, e1);
+        if (rep == 1) ms = t;
+      }
+      destroy_impl(p);
+      if (ms < best) {
+        best = ms;
+        best_s = Shape{c, w == occ ? 0 : w};
+      }
     }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   hipStreamSynchronize(st);
   hipFree(a);
-  *c_out = best_c;
+  *out = best_s;
   return rc;
 }
 
-int tuned_chunk(int n, int algo, bool plain, hipStream_t st, int* c_out) {
+// The shape for order n: from this process's tuning, the cache file, or a
+// new tuning run (saved to both).
+int tuned_shape(int n, int algo, bool plain, hipStream_t st, Shape* out) {
   int dev = 0;
   hipGetDevice(&dev);
   hipDeviceProp_t prop;
   hipError_t e = hipGetDeviceProperties(&prop, dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
-  TuneKey k{prop.gcnArchName, prop.multiProcessorCount, n, algo, plain ? 1 : 0};
+  TuneKey k{PH_BUILD_ID, prop.gcnArchName, prop.multiProcessorCount, n, algo, plain ? 1 : 0};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_cache_locked();
     auto it = g_tune.find(k);
     if (it != g_tune.end()) {
-      *c_out = it->second;
+      *out = it->second;
       return PH_OK;
     }
   }
-  int c = 0;
-  int rc = tune_chunk(n, algo, plain, st, &c);
+  Shape sh;
+  int rc = tune_shape(n, algo, plain, st, &sh);
   if (rc) return rc;
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune[k] = c;
+  g_tune[k] = sh;
   save_cache_locked();
-  *c_out = c;
+  *out = sh;
   return PH_OK;
 }
 
@@ -314,7 +355,7 @@ static hipError_t build_graph(PlanImpl* p, const Opts& o, const std::vector<std:
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds);
     if (e != hipSuccess) return e;
     per_cu = std::max(per_cu, 1);
-    if (o.waves > 0) per_cu = std::min(per_cu, o.waves);
+    if (p->bucket_waves[bk] > 0) per_cu = std::min(per_cu, p->bucket_waves[bk]);
     const int64_t nit = bucket_items[bk].second - bucket_items[bk].first;
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * per_cu, nit));
     MatDesc* dm = p->d_mats;
@@ -380,8 +421,9 @@ int plan_build(const int32_t* n_host, const int64_t* off_host, int64_t batch, co
     p->off[b] = off_host ? off_host[b] : run;
     run += (int64_t)p->n[b] * p->n[b];
   }
-  // chunk lengths
-  std::map<int, int> chosen;
+  // chunk lengths and waves per SIMD, per order: forced, from the options,
+  // or tuned
+  std::map<int, std::pair<int, int>>& chosen = p->shape;
   for (int64_t b = 0; b < batch; ++b) {
     const int n = p->n[b];
     if (n == 0) {
@@ -390,30 +432,47 @@ int plan_build(const int32_t* n_host, const int64_t* off_host, int64_t batch, co
     }
     if (c_force) {
       p->c[b] = c_force[b];
+      chosen.emplace(n, std::make_pair(c_force[b], o.waves));
       continue;
     }
     auto it = chosen.find(n);
     if (it == chosen.end()) {
-      int c = 0;
+      Shape sh;
       if (o.chunk_log2 > 0) {
-        c = o.chunk_log2;
+        sh.c = o.chunk_log2;
       } else {
-        int rc = tuned_chunk(n, o.algo, o.plain, st, &c);
+        int rc = tuned_shape(n, o.algo, o.plain, st, &sh);
         if (rc) {
           destroy_impl(p);
           return rc;
         }
       }
+      if (o.waves > 0) sh.waves = o.waves;
       const int nb = gray_bits(n, o.algo);
-      c = std::max(min_chunk_log2(nb), std::min(c, nb));
-      it = chosen.emplace(n, c).first;
+      sh.c = std::max(min_chunk_log2(nb), std::min(sh.c, nb));
+      it = chosen.emplace(n, std::make_pair(sh.c, sh.waves)).first;
     }
-    p->c[b] = it->second;
+    p->c[b] = it->second.first;
     if (p->ncols[b] != n) {
       // fewer columns: keep at least 256 chunks (one per lane of the four
       // wavefronts of a workgroup) where possible
       const int nb = gray_bits(p->ncols[b], o.algo);
       p->c[b] = std::max(min_chunk_log2(nb), std::min(p->c[b], std::max(min_chunk_log2(nb), nb - 8)));
+    }
+  }
+  // each bucket's sweep runs with the waves chosen for the order that holds
+  // most of its terms
+  {
+    std::map<int, double> terms_of_n;
+    for (int64_t b = 0; b < batch; ++b)
+      if (p->n[b] > 0) terms_of_n[p->n[b]] += std::ldexp(1.0, gray_bits(p->ncols[b], o.algo));
+    double most[NBUCKETS] = {};
+    for (auto& tn : terms_of_n) {
+      const int bk = bucket_of(tn.first);
+      if (bk >= 0 && tn.second > most[bk]) {
+        most[bk] = tn.second;
+        p->bucket_waves[bk] = chosen.count(tn.first) ? chosen[tn.first].second : o.waves;
+      }
     }
   }
   // order: bucket (largest first), then n descending, then batch index
@@ -524,22 +583,36 @@ static hipError_t set_io(PlanImpl* p, const double2* a, double2* out) {
 }
 
 int plan_exec(PlanImpl* p, const double2* a, double2* out, hipStream_t st) {
-  hipError_t e = set_io(p, a, out);
+  hipError_t e;
+  if (!p->done) {
+    e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
+  }
+  // the previous execution may still run on another stream: order this one
+  // after it (same stream: already ordered)
+  if (p->launched && st != p->last_stream) {
+    e = hipStreamWaitEvent(st, p->done, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+  }
+  e = set_io(p, a, out);
   if (e != hipSuccess) return hip_fail(e, "hipGraphExecKernelNodeSetParams");
   e = hipGraphLaunch(p->exec, st);
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   p->launched = true;
   p->last_stream = st;
+  int rc = PH_OK;
   if (!p->solo.empty()) {
     const int cus = num_cus();
     if (cus <= 0) return PH_EUNSUPPORTED;
     for (int64_t b : p->solo) {
       const int n = p->n[b];
-      const int rc = perm_single(a + p->off[b], n, n, out + b, p->opts, st, cus);
-      if (rc) return rc;
+      rc = perm_single(a + p->off[b], n, n, out + b, p->opts, st, cus);
+      if (rc) break;
     }
   }
-  return PH_OK;
+  e = hipEventRecord(p->done, st);
+  if (rc == PH_OK && e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  return rc;
 }
 
 double2* plan_table(PlanImpl* p, int64_t b) { return p->d_tabs + p->tab_off[b]; }
@@ -593,6 +666,17 @@ extern "C" int ph_plan_execute(void* plan, const ph_c128* A_packed, ph_c128* out
   if (dev != p->dev) return fail(PH_EINVAL, "plan was created on device %d, current device is %d", p->dev, dev);
   return plan_exec(p, reinterpret_cast<const double2*>(A_packed), reinterpret_cast<double2*>(out),
                    (hipStream_t)stream);
+}
+
+extern "C" int ph_plan_shape(const void* plan, int32_t n, int32_t* chunk_log2, int32_t* waves) {
+  if (!plan) return fail(PH_EINVAL, "plan is NULL");
+  if (!chunk_log2 || !waves) return fail(PH_EINVAL, "chunk_log2 or waves is NULL");
+  const auto* p = static_cast<const PlanImpl*>(plan);
+  auto it = p->shape.find(n);
+  if (it == p->shape.end()) return fail(PH_EINVAL, "the plan holds no matrix of order %d", n);
+  *chunk_log2 = it->second.first;
+  *waves = it->second.second;
+  return PH_OK;
 }
 
 extern "C" int ph_plan_destroy(void* plan) {

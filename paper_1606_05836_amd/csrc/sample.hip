@@ -228,7 +228,7 @@ extern "C" int ph_boson_sample(const ph_c128* U, int32_t m, int64_t ldu, const i
   if (cus <= 0) return PH_EUNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
   const int64_t G = std::min<int64_t>(nsamples, SAMPLE_GROUP);
-  // slot 4: in_modes | perms, uniforms (one group, as uploaded) | A | rows | mats | grad
+  // slot WS_SAMPLER: in_modes | perms, uniforms (one group, as uploaded) | A | rows | mats | grad
   size_t off[8];
   off[0] = 0;
   off[1] = off[0] + align256((size_t)n * 4);
@@ -239,7 +239,7 @@ extern "C" int ph_boson_sample(const ph_c128* U, int32_t m, int64_t ldu, const i
   off[6] = off[5] + align256((size_t)G * n * n * 16);
   off[7] = off[6] + align256((size_t)G * n * n * 16);
   void* ws = nullptr;
-  if ((rc = workspace_slot(st, off[7], 4, &ws))) return rc;
+  if ((rc = workspace_slot(st, off[7], WS_SAMPLER, &ws))) return rc;
   char* base = static_cast<char*>(ws);
   int32_t* d_in = reinterpret_cast<int32_t*>(base + off[0]);
   int32_t* d_perm = reinterpret_cast<int32_t*>(base + off[1]);

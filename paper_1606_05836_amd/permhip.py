@@ -21,10 +21,12 @@ PH_GLYNN, PH_RYSER = 0, 1
 PH_ACC_DD, PH_ACC_PLAIN = 0, 1
 PH_OK, PH_EINVAL, PH_ERANGE, PH_ENOMEM, PH_EHIP, PH_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PH_NMAX, PH_NMAX_GRAD = 52, 32
+PH_CHUNK_LOG2_MAX = 24
 PH_FLAG_UNGROUPED = 1
 PH_FLAG_UNSORTED = 2
+PH_FLAG_DU_FULL = 4
 
-EXPORTS = ("ph_perm", "ph_perm_ryser_paired", "ph_perm_chunk_log2", "ph_perm_partial", "ph_perm_combine", "ph_perm_batched", "ph_plan_create", "ph_plan_execute", "ph_plan_destroy",
+EXPORTS = ("ph_perm", "ph_perm_ryser_paired", "ph_perm_chunk_log2", "ph_perm_partial", "ph_perm_combine", "ph_perm_batched", "ph_plan_create", "ph_plan_execute", "ph_plan_destroy", "ph_plan_shape",
            "ph_perm_grad", "ph_perm_row_minors", "ph_boson_probs", "ph_boson_probs_grad", "ph_boson_sample", "ph_fp64_peak", "ph_last_error",
            "ph_version")
 
@@ -63,6 +65,7 @@ def lib() -> ctypes.CDLL:
     L.ph_plan_create.argtypes = [P(ctypes.c_int32), P(ctypes.c_int64), i64, op, vp, P(ctypes.c_void_p)]
     L.ph_plan_execute.argtypes = [vp, vp, vp, vp]
     L.ph_plan_destroy.argtypes = [vp]
+    L.ph_plan_shape.argtypes = [vp, i32, P(ctypes.c_int32), P(ctypes.c_int32)]
     L.ph_perm_grad.argtypes = [vp, i32, i64, vp, vp, vp, op, vp]
     L.ph_boson_probs.argtypes = [vp, i32, i64, P(ctypes.c_int32), i32, P(ctypes.c_int32), i64, dp, op, vp]
     L.ph_boson_probs_grad.argtypes = [vp, i32, i64, P(ctypes.c_int32), i32, P(ctypes.c_int32), i64, dp, dp, vp,
@@ -107,6 +110,17 @@ def _need_c128_cuda(name: str, t: torch.Tensor):
         raise TypeError(f"{name} must be a complex128 CUDA tensor")
 
 
+def _need_out(name: str, out: torch.Tensor, dtype: torch.dtype, numel: int, device: torch.device):
+    """The library writes `numel` elements of `dtype` at out's address: reject
+    anything else before the call (the C ABI cannot see device sizes)."""
+    if not isinstance(out, torch.Tensor) or out.dtype != dtype or not out.is_cuda:
+        raise TypeError(f"{name} must be a {dtype} CUDA tensor")
+    if out.device != device:
+        raise ValueError(f"{name} is on {out.device}, the input on {device}")
+    if out.numel() != numel or not out.is_contiguous():
+        raise ValueError(f"{name} must be contiguous with {numel} elements")
+
+
 def perm(a: torch.Tensor, algo="glynn", accum="dd", chunk_log2: int = 0, waves: int = 0,
          out: torch.Tensor | None = None) -> torch.Tensor:
     """Per(a) for an n x n complex128 matrix on the GPU (rows may be strided):
@@ -129,6 +143,8 @@ def perm(a: torch.Tensor, algo="glynn", accum="dd", chunk_log2: int = 0, waves: 
     lda = a.stride(0) if n > 0 else 1
     if out is None:
         out = torch.empty((), dtype=torch.complex128, device=a.device)
+    else:
+        _need_out("out", out, torch.complex128, 1, a.device)
     o = opts(algo, accum, chunk_log2, waves)
     check(lib().ph_perm(_ptr(a), n, lda, _ptr(out), ctypes.byref(o), _stream(a)))
     return out
@@ -147,6 +163,8 @@ def perm_ryser_paired(a: torch.Tensor, accum="dd", chunk_log2: int = 0,
         a = a.contiguous()
     if out is None:
         out = torch.empty((), dtype=torch.complex128, device=a.device)
+    else:
+        _need_out("out", out, torch.complex128, 1, a.device)
     o = opts("ryser", accum, chunk_log2)
     check(lib().ph_perm_ryser_paired(_ptr(a), n, a.stride(0) if n > 0 else 1, _ptr(out), ctypes.byref(o),
                                      _stream(a)))
@@ -180,8 +198,8 @@ def perm_partial(a: torch.Tensor, k_begin: int, k_end: int, algo="glynn", accum=
         a = a.contiguous()
     if out is None:
         out = torch.empty(4, dtype=torch.float64, device=a.device)
-    elif out.dtype != torch.float64 or not out.is_cuda or out.numel() != 4 or not out.is_contiguous():
-        raise ValueError("out must be 4 contiguous float64 values on the GPU")
+    else:
+        _need_out("out", out, torch.float64, 4, a.device)
     o = opts(algo, accum, chunk_log2, waves)
     check(lib().ph_perm_partial(_ptr(a), n, a.stride(0) if n > 0 else 1, int(k_begin), int(k_end), _ptr(out),
                                 ctypes.byref(o), _stream(a)))
@@ -197,6 +215,8 @@ def perm_combine(partials: torch.Tensor, n: int, algo="glynn", accum="dd",
     partials = partials.reshape(-1, 4).contiguous()
     if out is None:
         out = torch.empty((), dtype=torch.complex128, device=partials.device)
+    else:
+        _need_out("out", out, torch.complex128, 1, partials.device)
     o = opts(algo, accum)
     check(lib().ph_perm_combine(_ptr(partials), partials.shape[0], int(n), _ptr(out), ctypes.byref(o),
                                 _stream(partials)))
@@ -204,6 +224,9 @@ def perm_combine(partials: torch.Tensor, n: int, algo="glynn", accum="dd",
 
 
 def _pack(mats: Sequence[torch.Tensor]):
+    for m in mats:
+        if m.dim() != 2 or m.shape[0] != m.shape[1]:
+            raise ValueError(f"every matrix must be n x n, got shape {tuple(m.shape)}")
     ns = [int(m.shape[0]) for m in mats]
     flat = torch.cat([m.reshape(-1) for m in mats]) if mats else None
     return ns, flat
@@ -216,11 +239,19 @@ class Plan:
                  chunk_log2: int = 0, waves: int = 0, device=None):
         self.ns = [int(x) for x in ns]
         self.batch = len(self.ns)
-        self.device = torch.device(device or "cuda")
+        dev = torch.device(device or "cuda")
+        self.device = dev if dev.index is not None else torch.device("cuda", torch.cuda.current_device())
         self._n = (ctypes.c_int32 * max(1, self.batch))(*self.ns)
         self._off = None
+        # elements the plan reads from a_packed: the end of the last matrix
         if offsets is not None:
-            self._off = (ctypes.c_int64 * max(1, self.batch))(*[int(x) for x in offsets])
+            offs = [int(x) for x in offsets]
+            if len(offs) != self.batch:
+                raise ValueError("offsets needs one entry per matrix")
+            self._off = (ctypes.c_int64 * max(1, self.batch))(*offs)
+            self.elems = max((o + n * n for o, n in zip(offs, self.ns)), default=0)
+        else:
+            self.elems = sum(n * n for n in self.ns)
         self._opts = opts(algo, accum, chunk_log2, waves)
         h = ctypes.c_void_p(0)
         with torch.cuda.device(self.device):
@@ -233,10 +264,23 @@ class Plan:
         _need_c128_cuda("a_packed", a_packed)
         if not a_packed.is_contiguous():
             raise ValueError("a_packed must be contiguous")
+        if a_packed.device != self.device:
+            raise ValueError(f"a_packed is on {a_packed.device}, the plan on {self.device}")
+        if a_packed.numel() < self.elems:
+            raise ValueError(f"a_packed holds {a_packed.numel()} elements, the plan reads {self.elems}")
         if out is None:
             out = torch.empty(self.batch, dtype=torch.complex128, device=a_packed.device)
+        else:
+            _need_out("out", out, torch.complex128, self.batch, a_packed.device)
         check(lib().ph_plan_execute(self._h, _ptr(a_packed), _ptr(out), _stream(a_packed)))
         return out
+
+    def shape(self, n: int):
+        """(log2 chunk length, waves per SIMD; 0 = as many as fit) the plan
+        sweeps its order-n matrices with (ph_plan_shape)."""
+        c, w = ctypes.c_int32(0), ctypes.c_int32(0)
+        check(lib().ph_plan_shape(self._h, int(n), ctypes.byref(c), ctypes.byref(w)))
+        return int(c.value), int(w.value)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -289,6 +333,8 @@ def perm_grad(a: torch.Tensor, grad_out: torch.Tensor | None = None, accum="dd",
     g = None
     if grad_out is not None:
         _need_c128_cuda("grad_out", grad_out)
+        if grad_out.numel() != batch or grad_out.device != a3.device:
+            raise ValueError(f"grad_out needs {batch} values on {a3.device}")
         g = grad_out.reshape(batch).contiguous()
     p = torch.empty(batch, dtype=torch.complex128, device=a.device) if want_perm else None
     ga = torch.empty_like(a3)
@@ -343,22 +389,24 @@ def boson_probs(u: torch.Tensor, in_modes, patterns, algo="glynn", accum="dd", u
 
 
 def boson_probs_grad(u: torch.Tensor, in_modes, patterns, weights: torch.Tensor | None = None, accum="dd",
-                     ungrouped: bool = False):
+                     ungrouped: bool = False, full: bool = False):
     """(probs, dU): dU (m x n) holds dL/dU[:, in_modes[k]] in column k for
     L = sum_p w_p Pr[S -> T_p] (PyTorch's conjugate-Wirtinger convention).
-    ungrouped: one full sweep per pattern (PH_FLAG_UNGROUPED)."""
+    ungrouped: one full sweep per pattern (PH_FLAG_UNGROUPED).  full: dU is
+    the m x m gradient with respect to all of U, photons that share an input
+    mode added into its column (PH_FLAG_DU_FULL)."""
     u = _need_square_u(u)
     m = u.shape[0]
     ins, pats = _modes(in_modes, patterns, m)
     n, npat = ins.shape[0], pats.shape[0]
     probs = torch.empty(npat, dtype=torch.float64, device=u.device)
-    du = torch.empty((m, n), dtype=torch.complex128, device=u.device)
+    du = torch.empty((m, m if full else n), dtype=torch.complex128, device=u.device)
     w = None
     if weights is not None:
         w = weights.to(device=u.device, dtype=torch.float64).contiguous()
         if w.numel() != npat:
             raise ValueError("weights needs one entry per pattern")
-    o = opts("glynn", accum, flags=PH_FLAG_UNGROUPED if ungrouped else 0)
+    o = opts("glynn", accum, flags=(PH_FLAG_UNGROUPED if ungrouped else 0) | (PH_FLAG_DU_FULL if full else 0))
     check(lib().ph_boson_probs_grad(_ptr(u), m, u.stride(0), _i32p(ins), n, _i32p(pats), npat, _ptr(w),
                                     _ptr(probs), _ptr(du), du.stride(0), ctypes.byref(o), _stream(u)))
     return probs, du
@@ -375,6 +423,8 @@ def perm_row_minors(b: torch.Tensor, accum="dd", out: torch.Tensor | None = None
     flat = b.reshape(count, n, n + 1).contiguous()
     if out is None:
         out = torch.empty(flat.shape[0], n + 1, dtype=torch.complex128, device=b.device)
+    else:
+        _need_out("out", out, torch.complex128, flat.shape[0] * (n + 1), b.device)
     o = opts("glynn", accum)
     check(lib().ph_perm_row_minors(_ptr(flat), n, flat.shape[0], _ptr(out), ctypes.byref(o), _stream(b)))
     return out.reshape(*lead, n + 1)

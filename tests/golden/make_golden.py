@@ -81,11 +81,23 @@ def minors_jobs():
             yield f"grad_batch_m0_{i}_{j}", O.minor(a, i, j)
 
 
+def boson_jobs():
+    """U_{S,T} of three patterns of the 900-mode, 30-photon, 256-pattern
+    workload (main text, Eq. (1)); the library sweeps pattern 11 as 3888
+    multiplicity-grouped sweeps of 14 single-photon columns (the most any
+    grouped pattern takes), pattern 234 as one sweep over all 30 columns (the
+    call's sweep budget is spent by then), pattern 5 as 3 grouped sweeps of 28
+    columns.  Per is stored; the probability is |Per|^2 / prod t_j!."""
+    u, ins, pats = I.boson_workload()
+    for p in (11, 234, 5):
+        yield f"boson_workload_p{p}", O.gather_u_st(u, ins, pats[p])
+
+
 def main():
     which = sys.argv[1]
     workers = int(sys.argv[2]) if len(sys.argv) > 2 else O.host_cores()
     path = os.path.join(HERE, f"{which}_perms.txt")
-    jobs = {"haar": haar_jobs, "batch": batch_jobs, "minors": minors_jobs}[which]()
+    jobs = {"haar": haar_jobs, "batch": batch_jobs, "minors": minors_jobs, "boson": boson_jobs}[which]()
     _run(path, jobs, workers)
 
 

@@ -67,7 +67,8 @@ def test_argument_errors_are_reported_before_any_device_work(L):
     assert _perm(L, fake, 10, 10, fake, P.PhOpts(7, 0, 0, 0, 0)) == P.PH_EINVAL
     assert _perm(L, fake, 10, 10, fake, P.PhOpts(0, 5, 0, 0, 0)) == P.PH_EINVAL
     assert _perm(L, fake, 10, 10, fake, P.PhOpts(0, 0, 0, 9, 0)) == P.PH_EINVAL
-    assert _perm(L, fake, 10, 10, fake, P.PhOpts(0, 0, 0, 0, 4)) == P.PH_EINVAL  # unknown flag bit
+    assert _perm(L, fake, 10, 10, fake, P.PhOpts(0, 0, 0, 0, 8)) == P.PH_EINVAL  # unknown flag bit
+    assert _perm(L, fake, 10, 10, fake, P.PhOpts(0, 0, -1, 0, 0)) == P.PH_EINVAL  # negative chunk_log2
 
 
 def test_paired_ryser_argument_errors_before_any_device_work(L):
@@ -131,6 +132,9 @@ def test_boson_argument_errors_are_reported_before_any_device_work(L):
     g = list(range(P.PH_NMAX_GRAD + 1))
     assert grad(64, g, g, 1, 64) == P.PH_ERANGE
     assert grad(4, [0, 1], [0, 1], 1, 1) == P.PH_EINVAL  # lddu < n
+    full = P.PhOpts(0, 0, 0, 0, P.PH_FLAG_DU_FULL)
+    assert grad(4, [0, 1], [0, 1], 1, 3, o=full) == P.PH_EINVAL  # the m x m form needs lddu >= m
+    assert b"lddu=3 < 4" in L.ph_last_error()
     assert grad(4, [0, 1], [0, 1], 1, 2, du=None) == P.PH_EINVAL
     assert grad(4, [], [], 0, 1) == P.PH_EINVAL  # the gradient needs n >= 1
     assert grad(4, [0, 1], [0, 1], 1, 2, o=P.PhOpts(P.PH_RYSER, 0, 0, 0, 0)) == P.PH_EINVAL
@@ -151,6 +155,11 @@ def test_chunk_length_query(L):
     assert P.perm_chunk_log2(1, "ryser") == 1
     assert P.perm_chunk_log2(30, chunk_log2=9) == 9
     assert P.perm_chunk_log2(8, chunk_log2=40) == 7  # clamped to the 2^7 terms
+    # never above PH_CHUNK_LOG2_MAX, whatever the order and the request
+    assert P.perm_chunk_log2(50, chunk_log2=40) == P.PH_CHUNK_LOG2_MAX == 24
+    assert P.perm_chunk_log2(48, "ryser", chunk_log2=2**31 - 1) == P.PH_CHUNK_LOG2_MAX
+    assert P.perm_chunk_log2(26, chunk_log2=25) == P.PH_CHUNK_LOG2_MAX  # 2^25 terms, chunks of at most 2^24
+    assert P.perm_chunk_log2(20, chunk_log2=24) == 19  # the whole range
     assert P.gray_terms(40) == 1 << 39 and P.gray_terms(40, "ryser") == 1 << 40
     c = ctypes.c_int32(0)
     assert L.ph_perm_chunk_log2(0, None, ctypes.byref(c)) == P.PH_EINVAL
@@ -264,6 +273,32 @@ def test_trace_ranges_switch_on_without_side_effects(L):
     env = dict(os.environ, PERMHIP_ROCTX="1")
     r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
     assert r.returncode == 0 and r.stdout.strip() == "ok", r.stderr
+
+
+def test_header_constants_match_the_binding():
+    from paper_1606_05836_amd import permhip as P
+
+    txt = open(HEADER).read()
+    defs = dict(re.findall(r"^#define (PH_\w+) (\d+)u?", txt, re.M))
+    for name in ("PH_NMAX", "PH_NMAX_GRAD", "PH_CHUNK_LOG2_MAX", "PH_FLAG_UNGROUPED", "PH_FLAG_UNSORTED",
+                 "PH_FLAG_DU_FULL"):
+        assert int(defs[name]) == getattr(P, name), name
+
+
+def test_binding_rejects_mismatched_buffers_before_the_call():
+    # the C ABI cannot see device buffer sizes, so the binding checks them
+    import torch
+
+    from paper_1606_05836_amd import permhip as P
+
+    with pytest.raises(ValueError, match="n x n"):
+        P._pack([torch.zeros(3, 3, dtype=torch.complex128), torch.zeros(2, 3, dtype=torch.complex128)])
+    with pytest.raises(ValueError, match="n x n"):
+        P._pack([torch.zeros(4, dtype=torch.complex128)])
+    with pytest.raises(TypeError, match="CUDA"):
+        P._need_out("out", torch.zeros(1, dtype=torch.complex128), torch.complex128, 1, torch.device("cpu"))
+    with pytest.raises(TypeError, match="complex128"):
+        P._need_out("out", torch.zeros(1, dtype=torch.float64), torch.complex128, 1, torch.device("cpu"))
 
 
 def test_missing_library_fails_loudly(monkeypatch):

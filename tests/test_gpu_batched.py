@@ -146,9 +146,9 @@ def test_larger_size_buckets_exact(ph):
     assert abs(complex(got[3]) - want) <= 1e-14 * abs(want)
 
 
-@pytest.mark.skipif(__import__("os").environ.get("PH_LONG_TESTS") != "1",
-                    reason="a full n = 45 permanent takes about 2.5 minutes; set PH_LONG_TESTS=1")
+@pytest.mark.timeout(900)
 def test_batch_with_a_large_order_takes_the_two_lane_sweep(ph):
+    # a full n = 45 permanent: about 2.5 minutes
     # orders >= 45 in a batch are swept one by one after the plan's graph (two
     # lanes per term); the small ones stay in the graph
     mats = [I.diag_matrix(45, 1 + 1j), gauss_int(6, 1), I.haar1600_block(20)]
@@ -168,3 +168,57 @@ def test_two_permutations_closed_form_every_bucket(ph):
     small = [i for i, n in enumerate(ns) if n <= 36]
     got_r = ph.perm_batched([torch.from_numpy(mats[i]).to("cuda") for i in small], algo="ryser").cpu().numpy()
     assert [complex(x) for x in got_r] == [wants[i] for i in small]
+
+
+def test_plan_shape_options_and_errors(ph):
+    plan = ph.Plan([20] * 8 + [18] * 4, chunk_log2=9, waves=2)
+    assert plan.shape(20) == (9, 2) and plan.shape(18) == (9, 2)
+    with pytest.raises(ph.PermhipError, match="order 21"):
+        plan.shape(21)
+    plan.close()
+
+
+def test_autotuner_cache_round_trip(ph, tmp_path):
+    # the tuner times (chunk length, waves per SIMD) pairs and keeps the
+    # fastest per (build, device, order, formula, accumulation); the cache file
+    # carries them to the next process, and entries of another build are ignored
+    import json
+    import os
+    import subprocess
+    import sys
+
+    from paper_1606_05836_amd.build import build_id
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.txt"
+    code = ("import sys, json; sys.path.insert(0, %r)\n"
+            "import paper_1606_05836_amd as ph\n"
+            "p = ph.Plan([20] * 64 + [18] * 8)\n"
+            "print(json.dumps({'20': p.shape(20), '18': p.shape(18)}))\n" % root)
+    env = dict(os.environ, PERMHIP_TUNE_CACHE=str(cache))
+
+    def run():
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+        assert r.returncode == 0, r.stderr
+        return {int(k): tuple(v) for k, v in json.loads(r.stdout.strip().splitlines()[-1]).items()}
+
+    first = run()
+    lines = [l.split() for l in cache.read_text().splitlines()]
+    bid = build_id()
+    ours = {int(l[3]): l for l in lines if l[0] == bid}
+    assert set(ours) == {18, 20}
+    for n in (18, 20):
+        assert (int(ours[n][6]), int(ours[n][7])) == first[n]
+        assert ours[n][6] != "0"  # a chunk length was chosen
+    # a planted entry for n = 20 is taken as is; one of another build is not
+    l20 = ours[20]
+    planted = [bid] + l20[1:6] + ["7", "1"]
+    other = ["0" * 16] + l20[1:6] + ["5", "1"]
+    cache.write_text(" ".join(planted) + "\n" + " ".join(other) + "\n" + " ".join(ours[18]) + "\n")
+    second = run()
+    assert second[20] == (7, 1) and second[18] == first[18]
+    cache.write_text(" ".join(other) + "\n")
+    third = run()  # tunes n = 20 and 18 again: 2^5 is below every candidate
+    assert third[20][0] >= 6
+    kept = [l.split() for l in cache.read_text().splitlines()]
+    assert any(l[0] == "0" * 16 for l in kept) and any(l[0] == bid for l in kept)

@@ -11,6 +11,7 @@ import pytest
 
 import inputs as I
 import oracle as O
+from tests import _golden as G
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -230,6 +231,31 @@ def test_full_workload_forward_paths_agree(ph, full_workload):
     assert np.max(np.abs(np.abs(per) ** 2 / d - pf) / pf) <= 2 * PROB_TOL
 
 
+def test_full_workload_against_stored_exact(ph, full_workload):
+    # exact Per of three of the 256 thirty-photon patterns, written by the
+    # oracle (tests/golden/make_golden.py boson): pattern 11 (3888
+    # multiplicity-grouped sweeps of 14 single-photon columns), 234 (one sweep
+    # over all 30 columns: the call's grouped-sweep budget is spent by then)
+    # and 5 (3 grouped sweeps of 28 columns); Eq. (1) normalises by prod t_j!
+    from fractions import Fraction
+
+    u, ins, pats, w, pf, pg, du = full_workload
+    gold = G.load("boson")
+    checked = 0
+    for p in (11, 234, 5):
+        name = f"boson_workload_p{p}"
+        if name not in gold:
+            continue
+        a = O.gather_u_st(u, ins, pats[p])
+        ex_re, ex_im = G.value_for("boson", name, a)
+        d = O.occupation_factorials(ins) * O.occupation_factorials(pats[p])
+        exact = (ex_re * ex_re + ex_im * ex_im) / d
+        for got in (pf[p], pg[p]):
+            assert abs(Fraction(float(got)) - exact) <= Fraction(PROB_TOL) * exact, (p, got, float(exact))
+        checked += 1
+    assert checked >= 1, "stored exact values of the thirty-photon patterns are missing"
+
+
 def test_full_workload_row_and_column_laplace(ph, full_workload):
     # Laplace expansion of every Per_p along row i and along column k gives
     #   sum_k U[r, S_k] conj(dU[r, k]) = 2 sum_p w_p Pr_p t_{p, r}   (each output mode r)
@@ -286,3 +312,28 @@ def test_full_workload_phase_invariance(ph, full_workload):
     u2 = (ph_r[:, None] * u) * ph_c[None, :]
     p2 = ph.boson_probs(cuda(u2), ins, pats).cpu().numpy()
     assert np.max(np.abs(p2 - pf) / pf) <= 2 * PROB_TOL
+
+
+@pytest.mark.parametrize("m,ins,pat_seed", [(6, [1, 1, 4], 31), (14, [2, 2, 5, 6, 7, 8, 9, 10], 32),
+                                            (14, [0, 3, 3, 3, 4, 5, 6, 7, 8], 33)])
+def test_full_du_folds_photons_onto_columns(ph, m, ins, pat_seed):
+    # PH_FLAG_DU_FULL: the m x m gradient with respect to U, the columns of
+    # photons that share an input mode added in increasing photon order, the
+    # columns of modes without a photon zero; both paths (3 photons: one sweep
+    # per pattern; 8 and 9: multiplicity-grouped sweeps)
+    u = cuda(I.haar(m, 40))
+    n = len(ins)
+    rng = np.random.default_rng(pat_seed)
+    pats = np.sort(np.stack([rng.choice(m, n, replace=True) for _ in range(5)]), axis=1)
+    pats[0] = np.sort(np.concatenate([[pats[0, 0]] * 2, rng.choice(m, n - 2, replace=False)]))
+    w = cuda(rng.uniform(-1.0, 2.0, len(pats)))
+    pr, du = ph.boson_probs_grad(u, ins, pats, weights=w)
+    pf, full = ph.boson_probs_grad(u, ins, pats, weights=w, full=True)
+    assert full.shape == (m, m)
+    assert torch.equal(pr, pf)
+    du, full = du.cpu().numpy(), full.cpu().numpy()
+    want = np.zeros((m, m), dtype=np.complex128)
+    for k in range(n):
+        want[:, ins[k]] += du[:, k]
+    assert np.array_equal(full, want)
+    assert not np.any(full[:, [j for j in range(m) if j not in ins]])

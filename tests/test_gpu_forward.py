@@ -271,3 +271,22 @@ def test_two_permutations_closed_form_at_large_n(ph, n, algos):
     a, want = CF.two_permutations(n, 5000 + n)
     for algo in algos:
         assert run(ph, a, algo=algo) == want, algo
+
+
+def test_perm_after_every_other_entry_point_same_bits(ph):
+    # the entry points share per-stream workspace, each in a slot of its own:
+    # whatever ran before, ph_perm gives the same bits
+    a = torch.from_numpy(I.haar1600_block(21)).to("cuda")
+    ref = ph.perm(a).clone()
+    b = torch.from_numpy(I.grad_batch_20(4, 8)).to("cuda")
+    u_np, ins, pats = I.boson_workload(m=60, n=16, patterns=4)
+    u = torch.from_numpy(u_np).to("cuda")
+    perms, unis = ph.sample_inputs(4, 16, 5)
+    b13 = torch.from_numpy(I.submatrix(I.haar(64, 9), range(12), range(13))).to("cuda")
+    calls = [lambda: ph.perm_row_minors(b[:, :7, :]), lambda: ph.perm_row_minors(b13),
+             lambda: ph.perm_grad(b), lambda: ph.perm_batched(b), lambda: ph.boson_probs_grad(u, ins, pats),
+             lambda: ph.boson_probs_grad(u, ins, pats, full=True), lambda: ph.boson_sample(u, ins, perms=perms, uniforms=unis),
+             lambda: ph.perm_partial(a, 0, ph.gray_terms(21) // 2), lambda: ph.perm_ryser_paired(a)]
+    for f in calls:
+        f()
+        assert torch.equal(ph.perm(a), ref)

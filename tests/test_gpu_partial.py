@@ -185,11 +185,20 @@ def test_segmented_run_resumes_to_the_same_bits(ph, tmp_path):
     assert combine_shards(shards) == ref.total()
 
 
-@pytest.mark.parametrize("algo,n,c", [("glynn", 45, 6), ("glynn", 48, 6), ("glynn", 52, 6), ("ryser", 45, 6),
-                                      ("ryser", 47, 6), ("ryser", 52, 6), ("glynn", 48, 0)])
+@pytest.mark.parametrize("algo,n,c", [
+    # one lane per term: n = 33 (the first size range with three resident
+    # columns in batches), the n = 40 workload matrix itself, 41..44 (two
+    # resident columns), with short and default (2^12) chunks
+    ("glynn", 33, 6), ("glynn", 40, 6), ("glynn", 40, 0), ("glynn", 41, 6), ("glynn", 42, 6),
+    ("glynn", 43, 6), ("glynn", 44, 6), ("glynn", 44, 0), ("ryser", 33, 6), ("ryser", 40, 6),
+    ("ryser", 41, 6), ("ryser", 44, 6),
+    # two lanes per term from n = 45 (rows split in halves, odd n padded)
+    ("glynn", 45, 6), ("glynn", 48, 6), ("glynn", 52, 6), ("ryser", 45, 6),
+    ("ryser", 47, 6), ("ryser", 52, 6), ("glynn", 48, 0)])
 def test_large_n_haar_ranges_against_oracle(ph, algo, n, c):
-    # orders 45..52 sweep each term over two lanes (rows split in halves, odd n
-    # padded); short ranges high in the index space against the exact sums
+    # the Haar blocks of the n = 40 / 44 workload recipe (and the same recipe
+    # at the other orders): short ranges high in the index space, and the last
+    # chunk, against the exact sums of Eq. (S2) / Eq. (S1) over the same terms
     a = I.haar1600_block(n)
     g, d = O.to_gaussian_integers(a)
     scale = Fraction(1, d ** n)
@@ -288,3 +297,28 @@ def test_strided_rows_match_contiguous(ph, n, algo):
         assert torch.equal(ph.perm(view, algo=algo), ph.perm(dense, algo=algo))
     if n <= 5:
         assert O.rel_err(complex(ph.perm(view, algo=algo).cpu()), O.perm_exact(view.cpu().numpy())) <= 1e-12
+
+
+@pytest.mark.parametrize("algo", ["glynn", "ryser"])
+def test_longest_chunk_exact(ph, algo):
+    # the largest chunk length any call takes (PH_CHUNK_LOG2_MAX = 24; longer
+    # requests are clamped to it): n = 26 on D(P + Q), whose every term is an
+    # exact integer, in 2 (BB/FG) or 4 (Ryser) chunks of 2^24 terms
+    from tests._closed_forms import two_permutations
+
+    a, want = two_permutations(26, 2626)
+    assert ph.perm_chunk_log2(26, algo, chunk_log2=40) == ph.PH_CHUNK_LOG2_MAX == 24
+    got = complex(ph.perm(cuda(a), algo=algo, chunk_log2=40).cpu())
+    assert got == want
+
+
+def test_longest_chunk_two_lanes_exact(ph):
+    # the two-lane sweep (n >= 45) at the longest chunk: two chunks of 2^24
+    # terms of diag(1+i), n = 46, high in the index space; every term is
+    # (1+i)^46 = 2^23 i^23
+    n = 46
+    a = cuda(I.diag_matrix(n, 1 + 1j))
+    L = 1 << 24
+    kb = (1 << (n - 2)) + 5 * L
+    p = ph.perm_partial(a, kb, kb + 2 * L, chunk_log2=24).cpu().tolist()
+    assert complex(p[0] + p[1], p[2] + p[3]) == 2 * L * 2 ** 23 * 1j ** 23

@@ -68,3 +68,52 @@ def test_two_streams_in_flight(ph):
     for o1, o2 in outs:
         assert torch.equal(o1.cpu(), r1)
         assert torch.equal(o2.cpu(), r2)
+
+
+def test_one_plan_on_two_streams_back_to_back(ph):
+    # a plan's counters and partials are its own: a replay on a second stream
+    # must wait for the replay still running on the first
+    ns, mats = I.mixed_batch_16_26(batch=512)
+    flat = torch.cat([cuda(m).reshape(-1) for m in mats])
+    plan = ph.Plan(ns)
+    ref = plan(flat).cpu()
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    s2.wait_stream(torch.cuda.current_stream())
+    outs = []
+    for _ in range(4):
+        for s in (s1, s2):
+            with torch.cuda.stream(s):
+                outs.append(plan(flat))
+    s1.synchronize()
+    s2.synchronize()
+    for o in outs:
+        assert torch.equal(o.cpu(), ref)
+    plan.close()
+
+
+def test_binding_rejects_mismatched_device_buffers(ph):
+    # sizes the C ABI cannot see are checked by the binding before the call
+    a = cuda(I.haar1600_block(12))
+    with pytest.raises(ValueError, match="1 elements"):
+        ph.perm(a, out=torch.empty(2, dtype=torch.complex128, device="cuda"))
+    with pytest.raises(TypeError, match="complex128"):
+        ph.perm(a, out=torch.empty((), dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError, match="1 elements"):
+        ph.perm_ryser_paired(a, out=torch.empty(3, dtype=torch.complex128, device="cuda"))
+    with pytest.raises(ValueError, match="n x n"):
+        ph.perm_batched([a, a[:, :11]])
+    plan = ph.Plan([12, 12])
+    with pytest.raises(ValueError, match="reads 288"):
+        plan(a.reshape(-1))  # one matrix where the plan reads two
+    with pytest.raises(ValueError, match="2 elements"):
+        plan(torch.cat([a.reshape(-1), a.reshape(-1)]), out=torch.empty(1, dtype=torch.complex128, device="cuda"))
+    good = plan(torch.cat([a.reshape(-1), a.reshape(-1)]))
+    assert torch.equal(good[0], good[1])
+    plan.close()
+    with pytest.raises(ValueError, match="4 elements"):
+        ph.perm_partial(a, 0, 0, out=torch.empty(3, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError, match="1 elements"):
+        ph.perm_combine(torch.zeros(2, 4, dtype=torch.float64, device="cuda"), 12,
+                        out=torch.empty(4, dtype=torch.complex128, device="cuda"))
