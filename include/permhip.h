@@ -106,6 +106,19 @@ enum {
  * the formulas above. */
 int ph_perm(const ph_c128* A, int32_t n, int64_t lda, ph_c128* out, const ph_opts* opt, void* stream);
 
+/* ph_perm_noalloc: ph_perm without any device allocation, for callers that
+ * cannot allocate: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, errors and result bits as
+ * ph_perm.  ph_perm keeps its per-wave partial sums in workspace it grows with
+ * hipMalloc; this call keeps them in a fixed static device array of the
+ * library (262,144 bytes per device, held until the process ends; room for
+ * 8192 partial sums, every launch shape of a 256-CU MI355X), and fails with
+ * PH_ERANGE where a device would need more.  It allocates nothing, on the
+ * host's side or the device's, from its first call on.  All calls on one
+ * device share that array: calls that overlap on a device (concurrent
+ * streams) race and must be ordered by the caller. */
+int ph_perm_noalloc(const ph_c128* A, int32_t n, int64_t lda, ph_c128* out, const ph_opts* opt, void* stream);
+
 /* ph_perm_ryser_paired: *out (device, one complex128) = Per(A) by Ryser's
  * formula, Eq. (S1), in the load-balanced order of Supplementary
  * Algorithm S3: the loop runs over the 2^(n-1) subsets S of the first n - 1

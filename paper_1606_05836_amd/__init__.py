@@ -17,6 +17,7 @@ from .permhip import (  # noqa: F401
     lib,
     perm,
     perm_batched,
+    perm_noalloc,
     perm_chunk_log2,
     perm_combine,
     perm_partial,

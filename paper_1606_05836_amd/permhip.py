@@ -26,7 +26,7 @@ PH_FLAG_UNGROUPED = 1
 PH_FLAG_UNSORTED = 2
 PH_FLAG_DU_FULL = 4
 
-EXPORTS = ("ph_perm", "ph_perm_ryser_paired", "ph_perm_chunk_log2", "ph_perm_partial", "ph_perm_combine", "ph_perm_batched", "ph_plan_create", "ph_plan_execute", "ph_plan_destroy", "ph_plan_shape",
+EXPORTS = ("ph_perm", "ph_perm_noalloc", "ph_perm_ryser_paired", "ph_perm_chunk_log2", "ph_perm_partial", "ph_perm_combine", "ph_perm_batched", "ph_plan_create", "ph_plan_execute", "ph_plan_destroy", "ph_plan_shape",
            "ph_perm_grad", "ph_perm_row_minors", "ph_boson_probs", "ph_boson_probs_grad", "ph_boson_sample", "ph_fp64_peak", "ph_last_error",
            "ph_version")
 
@@ -57,6 +57,7 @@ def lib() -> ctypes.CDLL:
     op = ctypes.POINTER(PhOpts)
     P = ctypes.POINTER
     L.ph_perm.argtypes = [vp, i32, i64, vp, op, vp]
+    L.ph_perm_noalloc.argtypes = [vp, i32, i64, vp, op, vp]
     L.ph_perm_ryser_paired.argtypes = [vp, i32, i64, vp, op, vp]
     L.ph_perm_chunk_log2.argtypes = [i32, op, P(ctypes.c_int32)]
     L.ph_perm_partial.argtypes = [vp, i32, i64, ctypes.c_uint64, ctypes.c_uint64, vp, op, vp]
@@ -147,6 +148,23 @@ def perm(a: torch.Tensor, algo="glynn", accum="dd", chunk_log2: int = 0, waves: 
         _need_out("out", out, torch.complex128, 1, a.device)
     o = opts(algo, accum, chunk_log2, waves)
     check(lib().ph_perm(_ptr(a), n, lda, _ptr(out), ctypes.byref(o), _stream(a)))
+    return out
+
+
+def perm_noalloc(a: torch.Tensor, out: torch.Tensor, algo="glynn", accum="dd", chunk_log2: int = 0,
+                 waves: int = 0) -> torch.Tensor:
+    """Per(a) into the caller's 0-dim complex128 `out` through ph_perm_noalloc:
+    the library allocates nothing (its partial sums live in a static device
+    array shared by all calls on the device).  a: n x n, rows may be strided."""
+    _need_c128_cuda("a", a)
+    if a.dim() != 2 or a.shape[0] != a.shape[1]:
+        raise ValueError("a must be n x n")
+    _need_out("out", out, torch.complex128, 1, a.device)
+    n = a.shape[0]
+    if n > 0 and a.stride(1) != 1:
+        raise ValueError("a's rows must be contiguous (stride(1) == 1): no copy is made here")
+    o = opts(algo, accum, chunk_log2, waves)
+    check(lib().ph_perm_noalloc(_ptr(a), n, a.stride(0) if n > 0 else 1, _ptr(out), ctypes.byref(o), _stream(a)))
     return out
 
 
