@@ -30,6 +30,7 @@ namespace ph {
 int perm_grad_launch(const double2* A, int n, int64_t batch, const double2* gout, double2* pout, double2* grad,
                      const Opts& o, hipStream_t st, int cus);
 int grad_rows(int n);
+int grad_min_cols(int n);
 int grad_sweep(const double2* tabs, int n, int ncols, int64_t batch, const double2* gout, double2* pout,
                double2* grad, const Opts& o, hipStream_t st, int cus);
 
@@ -337,7 +338,9 @@ constexpr int GROUP_MIN_SINGLES = 5;
 constexpr int64_t GROUP_MAX_PER_PATTERN = 4096;
 constexpr int64_t GROUP_MAX_SWEEPS = (int64_t)1 << 17;
 
-static void plan_sweeps(const int32_t* patterns, int n, int64_t npat, bool ungrouped, Sweeps* sw) {
+// min_singles: the fewest single-photon modes (columns of a grouped sweep)
+// a pattern needs to be grouped.
+static void plan_sweeps(const int32_t* patterns, int n, int64_t npat, bool ungrouped, int min_singles, Sweeps* sw) {
   sw->pv.assign(npat + 1, 0);
   int64_t budget = GROUP_MAX_SWEEPS;
   std::vector<std::pair<int32_t, int>> cls;  // (mode, photons), first-appearance order
@@ -362,7 +365,7 @@ static void plan_sweeps(const int32_t* patterns, int n, int64_t npat, bool ungro
       else combos *= c.second + 1;
       if (combos > GROUP_MAX_PER_PATTERN) break;
     }
-    const bool group = !ungrouped && singles >= GROUP_MIN_SINGLES && combos > 1 &&
+    const bool group = !ungrouped && singles >= min_singles && combos > 1 &&
                        combos <= GROUP_MAX_PER_PATTERN && combos <= budget;
     if (!group) {
       // one sweep over all n columns (repeats included), weight 1
@@ -412,7 +415,7 @@ static void plan_sweeps(const int32_t* patterns, int n, int64_t npat, bool ungro
 static int boson_probs_grouped(hipStream_t st, const ph_c128* U, int64_t ldu, const int32_t* in_modes, int n,
                                const int32_t* patterns, int64_t npat, const Opts& o, double* probs) {
   Sweeps sw;
-  plan_sweeps(patterns, n, npat, o.ungrouped, &sw);
+  plan_sweeps(patterns, n, npat, o.ungrouped, GROUP_MIN_SINGLES, &sw);
   const int64_t V = (int64_t)sw.w.size();
   std::vector<int32_t> ns(V, n);
   // device layout in workspace slot WS_BOSON_GROUPED (the first NP_UP entries are uploaded)
@@ -560,7 +563,8 @@ static int boson_grad_grouped(hipStream_t st, const ph_c128* U, int32_t m, int64
                               ph_c128* dU, int64_t lddu, const Opts& o, int cus) {
   if ((int64_t)npat * n >= ((int64_t)1 << 31) - 1) return fail(PH_ERANGE, "n_patterns * n too large");
   Sweeps sw;
-  plan_sweeps(patterns, n, npat, o.ungrouped, &sw);
+  // a grouped gradient sweep walks at least grad_min_cols(n) columns
+  plan_sweeps(patterns, n, npat, o.ungrouped, std::max(GROUP_MIN_SINGLES, grad_min_cols(n)), &sw);
   const int64_t V = (int64_t)sw.w.size();
   const int rows = grad_rows(n);
   // groups of sweeps by column count; position of each sweep's results

@@ -133,7 +133,7 @@ __device__ __forceinline__ double reduce_scatter(double (&v)[CMAX]) {
 // Stored columns (K) and target wavefronts per SIMD per (rows per lane M,
 // lanes per term H).
 #ifndef PH_GRAD_K
-#define PH_GRAD_K(M, H) ((H) == 8 ? 4 : ((M) == 1 ? 1 : ((M) <= 4 ? 2 : 4)))
+#define PH_GRAD_K(M, H) ((H) == 8 ? 5 : ((M) == 1 ? 1 : ((M) <= 4 ? 2 : 5)))
 #endif
 #ifndef PH_GRAD_WAVES
 #define PH_GRAD_WAVES(M, H) ((H) == 8 ? ((M) <= 2 ? 3 : 2) : ((M) <= 1 ? 4 : ((M) <= 3 ? 3 : 2)))
@@ -183,7 +183,8 @@ struct GradLane {
   double2 r[M];
   double2 W[M];
   double2 G[GradShape<M, H>::K][M];
-  double2 colK[GradShape<M, H>::KR > 0 ? GradShape<M, H>::KR : 1][M];  // the lane's rows of columns 1..KR
+  double2 colK[GradShape<M, H>::KR][M];  // the lane's rows of columns 1..KR
+  double2 colv[M];                       // the next LDS-sourced step's column, read ahead
 };
 
 // Group sums: wt * W summed over the NG groups, for each lane position in the
@@ -392,6 +393,22 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
       // flips a bit >= K, chosen at run time.
       constexpr int NBK = 1 << K;
       const uint32_t nblk = 1u << (c - K);
+      // Steps whose column is not held in registers (Gray bits >= KR inside a
+      // block, and every block's first step) take it from colv, read from
+      // LDS one step ahead: during the term before, whose step flips a
+      // register-held bit (bit 0 at every odd offset), so the read has a
+      // whole term to arrive.  The reads are volatile and followed by a
+      // scheduling barrier so that the compiler keeps them there instead of
+      // next to their use.
+      static_assert(GS::KR >= 1, "every other step must take its column from registers");
+      auto prefetch = [&](int col) __attribute__((always_inline)) {
+        typedef const volatile __attribute__((address_space(3))) double lds_double;
+        lds_double* cp = (lds_double*)(tab + col * ROWS + row0);
+#pragma unroll
+        for (int ii = 0; ii < M; ++ii) L.colv[ii] = make_double2(cp[2 * ii], cp[2 * ii + 1]);
+        // (and the scheduler may not move them down past this point)
+        __builtin_amdgcn_sched_barrier(0);
+      };
       for (uint32_t m = 0; m < nblk; ++m) {
         const uint32_t tb = m << K;
         if (m != 0) {
@@ -411,21 +428,29 @@ __global__ __launch_bounds__(256, (GradShape<M, H>::WAVES)) void k_grad(GradArgs
           } else {
             group_sum_add<M, H>(L.W, 2.0 * sgu, ghat + (size_t)(b + 1) * 2 * ROWS, gidx);
           }
-          grad_update<M, H>(L, sgu, tab + (b + 1) * ROWS + row0);
+          grad_apply<M, H>(L, sgu, L.colv);
         }
         // the new value of bit K-1 (step 2^(K-1) of the block) comes from bit
         // K of k
         const double sg_top = (((k0 + tb) >> K) & 1) ? -1.0 : 1.0;
         static_for<0, NBK>([&](auto sc) {
           constexpr int so = decltype(sc)::value;
+          constexpr int bb = __builtin_ctz(so | NBK);
           if constexpr (so != 0) {
-            constexpr int bb = __builtin_ctz(so);
             const double sgu = bb + 1 < K ? (((so >> (bb + 1)) & 1) ? -1.0 : 1.0) : sg_top;
             stored_add<M, H>(L.G[bb], 2.0 * sgu, L.W);
             if constexpr (bb < GS::KR)
               grad_apply<M, H>(L, sgu, L.colK[bb]);
             else
-              grad_update<M, H>(L, sgu, tab + (bb + 1) * ROWS + row0);
+              grad_apply<M, H>(L, sgu, L.colv);
+          }
+          // the next step's column, if it comes from LDS
+          constexpr int bn = __builtin_ctz((so + 1) | NBK);
+          if constexpr (so + 1 < NBK) {
+            if constexpr (bn >= GS::KR) prefetch(bn + 1);
+          } else {
+            // the next block's first step (any column after the chunk's last block)
+            prefetch(m + 1 < nblk ? K + __builtin_ctz(m + 1) + 1 : 1);
           }
           grad_term<M, H, (so & 1) != 0, ACT>(L, act);
         });
@@ -596,6 +621,10 @@ int grad_rows(int n) {
   const GradLayout lay = grad_layout(n);
   return lay.H * lay.M;
 }
+
+// Fewest columns a gradient sweep of n rows walks: its blocks take 2^K terms,
+// K = the stored columns of n's layout, so ncols - 1 >= K.
+int grad_min_cols(int n) { return grad_layout(n).K + 1; }
 
 // Gradient sweeps over prebuilt tables: `batch` tables of ncols columns x
 // grad_rows(n) rows (T[0] = column 0, T[j] = -2 column j, rows >= n zero),
