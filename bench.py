@@ -22,6 +22,8 @@ usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 40]
                        [--no-cpu] [--no-extras] [--copy-probe MiB]
        python bench.py --precision 40,44   (precision study only)
        python bench.py --precision-allr    (the paper's all-r precision workload)
+       python bench.py --grad-ratio 20,24  (gradient against forward per order)
+       python bench.py --boson             (the boson-sampling workload only)
 """
 from __future__ import annotations
 
@@ -226,7 +228,18 @@ def extras(ph, dev, stream):
     # one device's share of the largest orders (two lanes per term), with
     # the full-sum time it implies on 1 and on 8 devices (a projection)
     res["large_share"] = {str(n): large_share(ph, dev, stream, n) for n in (48, 50)}
-    # boson sampling: Eq. (1) probabilities and their gradient
+    res["boson"] = boson(ph, dev, stream)
+    return res
+
+
+def boson(ph, dev, stream):
+    """The boson-sampling workload: Eq. (1) probabilities of 256 thirty-photon
+    collision patterns over 900 modes, their gradient with respect to U's
+    input columns, and 64 chain-rule samples."""
+    import torch
+
+    import inputs
+
     u, ins, pats = inputs.boson_workload()
     ud = torch.from_numpy(u).to(dev)
     ph.boson_probs(ud, ins, pats)
@@ -238,12 +251,11 @@ def extras(ph, dev, stream):
     ph.boson_sample(ud, ins, perms=perms[:2], uniforms=unis[:2])
     ps = _median(_event_ms(lambda: ph.boson_sample(ud, ins, perms=perms, uniforms=unis), 1, stream))
     _log(f"boson: 64 samples in {ps:.1f} ms")
-    res["boson"] = {
+    return {
         "workload": "U = Haar(900, 51), inputs in modes 0..29, 256 collision patterns (seed 52)",
         "probs_ms": pf, "probs_per_s": len(pats) / (pf / 1e3), "grad_ms": pg, "grad_fwd_ratio": pg / pf,
         "samples_64_ms": ps, "samples_per_s": 64 / (ps / 1e3),
     }
-    return res
 
 
 def config3(ph, dev, stream, a40, dd40):
@@ -476,6 +488,8 @@ def main():
     ap.add_argument("--checkpoint-dir", default="", help="where --paper-n45 keeps its segment checkpoints")
     ap.add_argument("--grad-ratio", default="", metavar="N,N",
                     help="print only the gradient/forward cost ratio at these orders")
+    ap.add_argument("--boson", action="store_true",
+                    help="print only the boson-sampling workload (probabilities, gradient, samples)")
     ap.add_argument("--precision-allr", action="store_true",
                     help="print only the precision study on the paper's all-r matrices")
     args = ap.parse_args()
@@ -506,6 +520,9 @@ def main():
         return
     if args.paper_n45:
         print(json.dumps({"paper_n45": paper_n45(ph, dev, args.checkpoint_dir)}), flush=True)
+        return
+    if args.boson:
+        print(json.dumps({"boson": boson(ph, dev, stream)}), flush=True)
         return
     if args.grad_ratio:
         ns = [int(x) for x in args.grad_ratio.split(",") if x.strip()]
