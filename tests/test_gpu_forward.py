@@ -290,3 +290,39 @@ def test_perm_after_every_other_entry_point_same_bits(ph):
     for f in calls:
         f()
         assert torch.equal(ph.perm(a), ref)
+
+
+def test_small_orders_every_call_completes(ph):
+    # Many calls of different sizes, grids, formulas and sums, on two streams
+    # (two workspaces) in turn: every call writes its result (out is poisoned
+    # with NaN before each) with the bits of the first call of the same kind.
+    rng = np.random.default_rng(77)
+    cases = []
+    for n in (1, 2, 5, 9, 13, 16, 17, 20, 24, 25):
+        cases.append((n, gauss_int(n, 700 + n, -1, 1) if n <= 14 else I.haar1600_block(n), {}))
+    cases.append((24, I.haar1600_block(24), {"chunk_log2": 4}))  # 2^19 chunks: a full grid
+    cases.append((20, I.haar1600_block(20), {"algo": "ryser"}))
+    cases.append((20, I.haar1600_block(20), {"accum": "plain"}))
+    mats = [dev(a) for _, a, _ in cases]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
+    first = {}
+    for rep in range(40):
+        order = rng.permutation(len(cases))
+        for i in order:
+            n, _, kw = cases[i]
+            st = streams[(rep + i) % 2]
+            with torch.cuda.stream(st):
+                out = torch.full((), complex(float("nan"), float("nan")), dtype=torch.complex128, device="cuda")
+                ph.perm(mats[i], out=out, **kw)
+                v = complex(out.cpu())
+            assert v == v, f"case {i} (n = {n}) left no result on call {rep}"
+            if i in first:
+                assert v == first[i], f"case {i} (n = {n}): {v} != {first[i]} on call {rep}"
+            else:
+                first[i] = v
+    # the integer cases are exact (each certified exact in binary64)
+    for i, (n, a, kw) in enumerate(cases):
+        if n <= 14 and not kw:
+            assert O.certify_int_exact(a)["certified"], n
+            assert first[i] == c_exact(O.perm_exact(a)), f"n = {n}"
