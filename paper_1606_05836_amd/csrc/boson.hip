@@ -16,7 +16,6 @@
 #include <cstring>
 #include <map>
 #include <mutex>
-#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -384,26 +383,35 @@ static void plan_sweeps(const int32_t* patterns, int n, int64_t npat, bool ungro
     std::vector<std::pair<int32_t, int>> coll;
     for (auto& c : cls)
       if (c.second > 1) coll.push_back(c);
-    std::vector<int> k(coll.size(), 0);
+    // signed binomials (-1)^k C(mu, k) of each collided mode
+    const size_t nl = coll.size();
+    std::vector<std::vector<double>> sbin(nl);
+    for (size_t l = 0; l < nl; ++l) {
+      const int mu = coll[l].second;
+      for (int kk = 0; kk <= mu; ++kk) {
+        double binom = 1.0;
+        for (int z = 0; z < kk; ++z) binom = binom * (mu - z) / (z + 1);
+        sbin[l].push_back((kk & 1) ? -binom : binom);
+      }
+    }
+    // k in mixed radix, first collided mode fastest, stepped like an odometer
+    std::vector<int> k(nl, 0);
     for (int64_t q = 0; q < combos; ++q) {
-      // k in mixed radix (first collided mode fastest)
-      int64_t r = q;
       double w = 1.0;
       sw->vcoef.push_back((int32_t)sw->coefs.size());
-      sw->vncoef.push_back((int32_t)coll.size());
-      for (size_t l = 0; l < coll.size(); ++l) {
-        const int mu = coll[l].second;
-        k[l] = (int)(r % (mu + 1));
-        r /= mu + 1;
-        double binom = 1.0;
-        for (int z = 0; z < k[l]; ++z) binom = binom * (mu - z) / (z + 1);
-        w *= (k[l] & 1) ? -binom : binom;
+      sw->vncoef.push_back((int32_t)nl);
+      for (size_t l = 0; l < nl; ++l) {
+        w *= sbin[l][k[l]];
         sw->collmodes.push_back(coll[l].first);
-        sw->coefs.push_back((double)(mu - 2 * k[l]));
+        sw->coefs.push_back((double)(coll[l].second - 2 * k[l]));
       }
       sw->vcol.push_back(col_off);
       sw->vncols.push_back(singles);
       sw->w.push_back(w);
+      for (size_t l = 0; l < nl; ++l) {
+        if (++k[l] <= coll[l].second) break;
+        k[l] = 0;
+      }
     }
   }
   sw->pv[npat] = (int32_t)sw->w.size();
@@ -522,19 +530,53 @@ __global__ void k_boson_gtab(const double2* __restrict__ u, int64_t ldu, const i
   }
 }
 
-// D[e][k] = sum over entry e's contributions, in order, of coef * cm[pos + k * stride]
-__global__ void k_boson_class_grad(const double2* __restrict__ cm, const int32_t* __restrict__ cstart,
-                                   const int64_t* __restrict__ cpos, const int32_t* __restrict__ cstride,
-                                   const double* __restrict__ ccoef, int64_t nent, int n, double2* __restrict__ D) {
+// One (pattern, output mode) entry of the gradient: which columns of the
+// pattern's sweeps hold the mode.
+enum : int32_t {
+  ENT_SINGLE = 0,    // grouped pattern, single-photon mode: column idx of every sweep
+  ENT_COLLIDED = 1,  // grouped pattern, collided mode idx: column 0 of every sweep, times its coefficient
+  ENT_WHOLE = 2      // pattern swept whole: every column of its one sweep that holds the mode
+};
+struct EntryDesc {
+  int32_t pat, kind, idx, mode;
+};
+
+// D[e][k] = sum over the sweeps v of entry e's pattern, in order, of
+// w_v * (coefficient) * cm_v[k][column] for the columns of v that hold the
+// entry's mode (cm_v: the n x ncols column derivatives of sweep v).
+__global__ void k_boson_class_grad(const double2* __restrict__ cm, const int64_t* __restrict__ moff,
+                                   const int32_t* __restrict__ vncols, const int32_t* __restrict__ vcol,
+                                   const int32_t* __restrict__ colmodes, const int32_t* __restrict__ vcoef,
+                                   const double* __restrict__ coefs, const double* __restrict__ w,
+                                   const int32_t* __restrict__ pv, const EntryDesc* __restrict__ ent, int64_t nent,
+                                   int n, double2* __restrict__ D) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= nent * n) return;
   const int64_t e = t / n;
   const int k = (int)(t % n);
+  const EntryDesc d = ent[e];
   double sr = 0.0, si = 0.0;
-  for (int32_t q = cstart[e]; q < cstart[e + 1]; ++q) {
-    const double2 x = cm[cpos[q] + (int64_t)k * cstride[q]];
-    sr = fma(ccoef[q], x.x, sr);
-    si = fma(ccoef[q], x.y, si);
+  for (int32_t v = pv[d.pat]; v < pv[d.pat + 1]; ++v) {
+    const int nc = vncols[v];
+    const double2* c = cm + moff[v] + (int64_t)k * nc;
+    if (d.kind == ENT_SINGLE) {
+      const double2 x = c[d.idx];
+      sr = fma(w[v], x.x, sr);
+      si = fma(w[v], x.y, si);
+    } else if (d.kind == ENT_COLLIDED) {
+      const double cf = w[v] * coefs[vcoef[v] + d.idx];
+      const double2 x = c[0];
+      sr = fma(cf, x.x, sr);
+      si = fma(cf, x.y, si);
+    } else {
+      const int32_t* cmd = colmodes + vcol[v];
+      for (int j = 0; j < nc; ++j)
+        if (cmd[j] == d.mode) {
+          const double2 x = c[j];
+          sr = fma(w[v], x.x, sr);
+          si = fma(w[v], x.y, si);
+        }
+    }
   }
   D[t] = make_double2(sr, si);
 }
@@ -582,45 +624,36 @@ static int boson_grad_grouped(hipStream_t st, const ph_c128* U, int32_t m, int64
       mtot += (int64_t)n * g.first;
     }
   }
-  // (pattern, output mode) entries and their contributions
+  // (pattern, output mode) entries, patterns in order, modes in order of
+  // first appearance; each names the columns of its pattern's sweeps that
+  // hold its mode
   std::vector<int32_t> ent_pat, ent_mode;
-  std::vector<std::vector<std::tuple<int64_t, int32_t, double>>> contrib;
+  std::vector<EntryDesc> ent;
+  ent.reserve((size_t)npat * n);
   for (int64_t p = 0; p < npat; ++p) {
     const int32_t* t = patterns + p * n;
-    const int32_t e0 = (int32_t)ent_pat.size();
-    auto entry = [&](int32_t mode) -> int32_t {
-      for (int32_t e = e0; e < (int32_t)ent_pat.size(); ++e)
-        if (ent_mode[e] == mode) return e;
-      ent_pat.push_back((int32_t)p);
-      ent_mode.push_back(mode);
-      contrib.emplace_back();
-      return (int32_t)ent_pat.size() - 1;
-    };
-    for (int i = 0; i < n; ++i) entry(t[i]);
-    for (int32_t v = sw.pv[p]; v < sw.pv[p + 1]; ++v) {
-      const int nc = sw.vncols[v];
-      const int32_t* cmodes = sw.colmodes.data() + sw.vcol[v];
-      for (int j = 0; j < nc; ++j) contrib[entry(cmodes[j])].emplace_back(moff[v] + j, nc, sw.w[v]);
-      for (int q = 0; q < sw.vncoef[v]; ++q) {
-        const int32_t cidx = sw.vcoef[v] + q;
-        contrib[entry(sw.collmodes[cidx])].emplace_back(moff[v], nc, sw.w[v] * sw.coefs[cidx]);
+    const int32_t e0 = (int32_t)ent.size();
+    const int32_t v0 = sw.pv[p];
+    const bool grouped = sw.vncoef[v0] > 0;
+    for (int i = 0; i < n; ++i) {
+      bool seen = false;
+      for (int32_t e = e0; e < (int32_t)ent.size() && !seen; ++e) seen = ent[e].mode == t[i];
+      if (seen) continue;
+      EntryDesc d{(int32_t)p, ENT_WHOLE, 0, t[i]};
+      if (grouped) {
+        d.kind = -1;
+        for (int j = 0; j < sw.vncols[v0] && d.kind < 0; ++j)
+          if (sw.colmodes[sw.vcol[v0] + j] == t[i]) d = EntryDesc{(int32_t)p, ENT_SINGLE, j, t[i]};
+        for (int q = 0; q < sw.vncoef[v0] && d.kind < 0; ++q)
+          if (sw.collmodes[sw.vcoef[v0] + q] == t[i]) d = EntryDesc{(int32_t)p, ENT_COLLIDED, q, t[i]};
+        if (d.kind < 0) return fail(PH_EINVAL, "pattern %lld: mode %d has no sweep column", (long long)p, t[i]);
       }
+      ent.push_back(d);
+      ent_pat.push_back((int32_t)p);
+      ent_mode.push_back(t[i]);
     }
   }
-  const int64_t E = (int64_t)ent_pat.size();
-  std::vector<int32_t> cstart(E + 1, 0), cstride;
-  std::vector<int64_t> cpos;
-  std::vector<double> ccoef;
-  for (int64_t e = 0; e < E; ++e) {
-    cstart[e] = (int32_t)cpos.size();
-    for (auto& c : contrib[e]) {
-      cpos.push_back(std::get<0>(c));
-      cstride.push_back(std::get<1>(c));
-      ccoef.push_back(std::get<2>(c));
-    }
-  }
-  cstart[E] = (int32_t)cpos.size();
-  const int64_t C = (int64_t)cpos.size();
+  const int64_t E = (int64_t)ent.size();
   std::vector<int32_t> mstart(m + 1, 0), mlist(E);
   for (int64_t e = 0; e < E; ++e) mstart[ent_mode[e] + 1]++;
   for (int r = 0; r < m; ++r) mstart[r + 1] += mstart[r];
@@ -630,26 +663,24 @@ static int boson_grad_grouped(hipStream_t st, const ph_c128* U, int32_t m, int64
   }
   // device layout (workspace slot WS_BOSON_GROUPED)
   auto one = [](size_t x) { return std::max<size_t>(x, 1); };
-  enum { P_IN, P_PAT, P_VCOL, P_VCOEF, P_VNCOEF, P_COLM, P_COLLM, P_PV, P_VLIST, P_VPOS, P_CSTART, P_CSTRIDE,
-         P_ENTPAT, P_MSTART, P_MLIST, P_COEFS, P_W, P_CCOEF, P_CPOS, NP_UP,
+  enum { P_IN, P_PAT, P_VCOL, P_VCOEF, P_VNCOEF, P_VNCOLS, P_COLM, P_COLLM, P_PV, P_VLIST, P_VPOS, P_ENTPAT,
+         P_MSTART, P_MLIST, P_ENT, P_COEFS, P_W, P_MOFF, NP_UP,
          B_TAB = NP_UP, B_CM, B_POUT, B_PERMS, B_GPERM, B_D, NB_ALL };
   size_t sz[NB_ALL] = {};
   sz[P_IN] = one(n) * 4;
   sz[P_PAT] = one(npat * n) * 4;
-  sz[P_VCOL] = sz[P_VCOEF] = sz[P_VNCOEF] = one(V) * 4;
+  sz[P_VCOL] = sz[P_VCOEF] = sz[P_VNCOEF] = sz[P_VNCOLS] = one(V) * 4;
   sz[P_COLM] = one(sw.colmodes.size()) * 4;
   sz[P_COLLM] = one(sw.collmodes.size()) * 4;
   sz[P_PV] = one(npat + 1) * 4;
   sz[P_VLIST] = sz[P_VPOS] = one(V) * 4;
-  sz[P_CSTART] = one(E + 1) * 4;
-  sz[P_CSTRIDE] = one(C) * 4;
   sz[P_ENTPAT] = one(E) * 4;
   sz[P_MSTART] = one(m + 1) * 4;
   sz[P_MLIST] = one(E) * 4;
+  sz[P_ENT] = one(E) * sizeof(EntryDesc);
   sz[P_COEFS] = one(sw.coefs.size()) * 8;
   sz[P_W] = one(V) * 8;
-  sz[P_CCOEF] = one(C) * 8;
-  sz[P_CPOS] = one(C) * 8;
+  sz[P_MOFF] = one(V) * 8;
   sz[B_TAB] = one(max_tab) * 16;
   sz[B_CM] = one(mtot) * 16;
   sz[B_POUT] = one(V) * 16;
@@ -670,20 +701,19 @@ static int boson_grad_grouped(hipStream_t st, const ph_c128* U, int32_t m, int64
                            {sw.vcol.data(), (size_t)V * 4},
                            {sw.vcoef.data(), (size_t)V * 4},
                            {sw.vncoef.data(), (size_t)V * 4},
+                           {sw.vncols.data(), (size_t)V * 4},
                            {sw.colmodes.data(), sw.colmodes.size() * 4},
                            {sw.collmodes.data(), sw.collmodes.size() * 4},
                            {sw.pv.data(), (size_t)(npat + 1) * 4},
                            {vlist.data(), (size_t)V * 4},
                            {vpos.data(), (size_t)V * 4},
-                           {cstart.data(), (size_t)(E + 1) * 4},
-                           {cstride.data(), (size_t)C * 4},
                            {ent_pat.data(), (size_t)E * 4},
                            {mstart.data(), (size_t)(m + 1) * 4},
                            {mlist.data(), (size_t)E * 4},
+                           {ent.data(), (size_t)E * sizeof(EntryDesc)},
                            {sw.coefs.data(), sw.coefs.size() * 8},
                            {sw.w.data(), (size_t)V * 8},
-                           {ccoef.data(), (size_t)C * 8},
-                           {cpos.data(), (size_t)C * 8}};
+                           {moff.data(), (size_t)V * 8}};
   if ((rc = upload_at(st, d, off, pc, NP_UP))) return rc;
   // one gradient sweep launch per column count
   int64_t first = 0;
@@ -705,8 +735,9 @@ static int boson_grad_grouped(hipStream_t st, const ph_c128* U, int32_t m, int64
                      weights, probs, C128(B_GPERM));
   if (E > 0)
     hipLaunchKernelGGL(k_boson_class_grad, dim3((unsigned)((E * n + 255) / 256)), dim3(256), 0, st, C128(B_CM),
-                       I32(P_CSTART), reinterpret_cast<int64_t*>(d + off[P_CPOS]), I32(P_CSTRIDE), F64(P_CCOEF), E, n,
-                       C128(B_D));
+                       reinterpret_cast<const int64_t*>(d + off[P_MOFF]), I32(P_VNCOLS), I32(P_VCOL), I32(P_COLM),
+                       I32(P_VCOEF), F64(P_COEFS), F64(P_W), I32(P_PV),
+                       reinterpret_cast<const EntryDesc*>(d + off[P_ENT]), E, n, C128(B_D));
   const int64_t tot = (int64_t)m * n;
   hipLaunchKernelGGL(k_boson_scatter_entries, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, C128(B_D),
                      C128(B_GPERM), I32(P_ENTPAT), I32(P_MSTART), I32(P_MLIST), m, n, reinterpret_cast<double2*>(dU),
