@@ -97,6 +97,10 @@ def cpu_baseline(a, n: int, seconds: float = 15.0):
         "kind": "oracle",
         "sample": f"exact Python-integer Glynn walk over Gray indices [0, {terms}) of the same n={n} matrix "
                   f"({terms} of 2^{n - 1} terms, {dt:.1f} s, contiguous ranges per process)",
+        # the single-process rate of the calibration, and the whole sum at
+        # these rates (extrapolated, not run)
+        "us_per_term_one_core": per_term * 1e6,
+        "extrapolated_full_sum_s": (1 << (n - 1)) / (terms / dt),
     }
 
 

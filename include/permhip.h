@@ -125,7 +125,8 @@ int ph_perm_noalloc(const ph_c128* A, int32_t n, int64_t lda, ph_c128* out, cons
  * columns (in Gray order here) and takes with each S the term of its
  * complement among all n columns, so every subset is summed once.  A as
  * ph_perm (device, lda >= n), 0 <= n <= 32.  opt: accum and chunk_log2 are
- * used (a chunk is 2^chunk_log2 loop indices); algo and waves are checked as
+ * used (a chunk is 2^chunk_log2 loop indices, at least 16 from n = 19, where
+ * two lanes share an index and step in blocks of 16); algo and waves are checked as
  * for ph_perm but do not change the computation.
  * Errors: PH_EINVAL (NULL pointer, lda < n, n < 0, bad options), PH_ERANGE
  * (n > 32), PH_EHIP.  Asynchronous on `stream`; deterministic. */

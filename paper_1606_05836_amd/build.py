@@ -114,6 +114,8 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
             return True
         if "k_gradILi" in kernel:  # csrc/grad.hip: DPP and lane-swap exchanges every term
             return True
+        if "k_ryser_paired_2l" in kernel:  # csrc/ryser_paired.hip: resident columns of the two-lane walk
+            return True
         m = re.search(r"sweep_\w*?ILi(\d+)E(Li(\d+)E)?", kernel)
         if not m:
             return False
@@ -130,7 +132,8 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     # (AGPR copies included) is allowed there, and no per-lane array may have
     # been left in scratch memory (a register array the compiler could not
     # keep in registers, e.g. one indexed through a merged pointer)
-    bad = [k for k, v in report.items() if ("sweep" in k or "k_minors" in k or "k_gradILi" in k) and _uses_dpp(k) and (
+    bad = [k for k, v in report.items() if ("sweep" in k or "k_minors" in k or "k_gradILi" in k
+                                             or "k_ryser_paired_2l" in k) and _uses_dpp(k) and (
         v.get("VGPRs Spill", "0") != "0" or v.get("SGPRs Spill", "0") != "0" or v.get("AGPRs", "0") != "0"
         or v.get("ScratchSize [bytes/lane]", "0") != "0")]
     if bad:

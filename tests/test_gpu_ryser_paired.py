@@ -112,3 +112,12 @@ def test_two_permutations_closed_form_bit_exact(ph, n):
     a, want = CF.two_permutations(n, 4000 + n)
     assert complex(ph.perm_ryser_paired(cuda(a)).cpu()) == want
     assert complex(ph.perm(cuda(a)).cpu()) == want  # BB/FG on the same matrix
+
+
+@pytest.mark.parametrize("c", [2, 4, 5, 9, 14])
+def test_two_lane_chunk_lengths_bit_exact(ph, c):
+    # the two-lane walk (n >= 19) steps in blocks of 16: shorter requested
+    # chunks become 16 indices; every chunk length gives the exact closed form
+    a, want = CF.two_permutations(23, 5000 + c)
+    assert complex(ph.perm_ryser_paired(cuda(a), chunk_log2=c).cpu()) == want
+    assert complex(ph.perm_ryser_paired(cuda(a), chunk_log2=c, accum="plain").cpu()) == want
