@@ -256,7 +256,7 @@ def test_full_workload_against_stored_exact(ph, full_workload):
         for got in (pf[p], pg[p]):
             assert abs(Fraction(float(got)) - exact) <= Fraction(PROB_TOL) * exact, (p, got, float(exact))
         checked += 1
-    assert checked >= 2, "stored exact values of the thirty-photon patterns are missing"
+    assert checked == 3, "stored exact values of the thirty-photon patterns are missing"
 
 
 def test_full_workload_row_and_column_laplace(ph, full_workload):
