@@ -2,6 +2,7 @@
 // chunk-length tuning) and one hipGraph per plan holding the reset, prep,
 // per-bucket sweep and finalize kernels.
 #include <hip/hip_runtime.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <cmath>
@@ -187,13 +188,25 @@ static void load_cache_locked() {
   }
 }
 
+// Written to a file of this process's own and renamed over the cache, so a
+// process reading the cache never sees a half-written file (with several
+// writers the last rename wins; every entry it drops is tuned again).
 static void save_cache_locked() {
   const std::string path = cache_path();
   if (path.empty()) return;
-  std::ofstream f(path, std::ios::trunc);
-  for (auto& kv : g_tune)
-    f << kv.first.build << ' ' << kv.first.arch << ' ' << kv.first.cus << ' ' << kv.first.n << ' ' << kv.first.algo
-      << ' ' << kv.first.plain << ' ' << kv.second.c << ' ' << kv.second.waves << '\n';
+  const std::string tmp = path + ".tmp." + std::to_string((long long)getpid());
+  {
+    std::ofstream f(tmp, std::ios::trunc);
+    for (auto& kv : g_tune)
+      f << kv.first.build << ' ' << kv.first.arch << ' ' << kv.first.cus << ' ' << kv.first.n << ' '
+        << kv.first.algo << ' ' << kv.first.plain << ' ' << kv.second.c << ' ' << kv.second.waves << '\n';
+    if (!f) {
+      f.close();
+      std::remove(tmp.c_str());
+      return;
+    }
+  }
+  if (std::rename(tmp.c_str(), path.c_str()) != 0) std::remove(tmp.c_str());
 }
 
 int plan_build(const int32_t* n_host, const int64_t* off_host, int64_t batch, const Opts& o, const int32_t* c_force,

@@ -222,3 +222,5 @@ def test_autotuner_cache_round_trip(ph, tmp_path):
     assert third[20][0] >= 6
     kept = [l.split() for l in cache.read_text().splitlines()]
     assert any(l[0] == "0" * 16 for l in kept) and any(l[0] == bid for l in kept)
+    # each process wrote a file of its own and renamed it over the cache
+    assert sorted(x.name for x in tmp_path.iterdir()) == ["tune.txt"]
