@@ -101,7 +101,19 @@ def cpu_baseline(a, n: int, seconds: float = 15.0):
         # these rates (extrapolated, not run)
         "us_per_term_one_core": per_term * 1e6,
         "extrapolated_full_sum_s": (1 << (n - 1)) / (terms / dt),
+        "cpu_model": _cpu_model(),
     }
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _log(msg: str):
