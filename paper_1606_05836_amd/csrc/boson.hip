@@ -23,6 +23,7 @@
 #include "permhip.h"
 #include "ph_host.hpp"
 #include "ph_internal.hpp"
+#include "sweep.hpp"
 
 namespace ph {
 
@@ -301,15 +302,21 @@ __global__ void k_boson_vtab(const double2* __restrict__ u, int64_t ldu, const i
   }
 }
 
-// perms[p] = sum over the pattern's sweeps, in order, of w_v * vout[vpos[v]]
-// (vpos NULL: vout in sweep order)
-__global__ void k_boson_combine(const double2* __restrict__ vout, const int32_t* __restrict__ vpos,
-                                const double* __restrict__ w, const int32_t* __restrict__ pv, int64_t npat, int plain,
-                                double2* __restrict__ perms) {
-  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// perms[p] = sum over the pattern's sweeps of w_v * vout[vpos[v]] (vpos
+// NULL: vout in sweep order), one wavefront per pattern: lane t sums a
+// contiguous slice of the sweeps in order, then the lanes meet in a fixed
+// butterfly, so the result depends only on the inputs.
+__global__ __launch_bounds__(64) void k_boson_combine(const double2* __restrict__ vout,
+                                                      const int32_t* __restrict__ vpos, const double* __restrict__ w,
+                                                      const int32_t* __restrict__ pv, int64_t npat, int plain,
+                                                      double2* __restrict__ perms) {
+  const int64_t p = blockIdx.x;
   if (p >= npat) return;
+  const int t = threadIdx.x;
+  const int64_t v0 = pv[p], cnt = pv[p + 1] - v0;
+  const int64_t b0 = v0 + cnt * t / 64, b1 = v0 + cnt * (t + 1) / 64;
   dd2 s = {0.0, 0.0, 0.0, 0.0};
-  for (int32_t v = pv[p]; v < pv[p + 1]; ++v) {
+  for (int64_t v = b0; v < b1; ++v) {
     const double2 x = vout[vpos ? vpos[v] : v];
     if (plain) {
       s.hr = fma(w[v], x.x, s.hr);
@@ -319,7 +326,8 @@ __global__ void k_boson_combine(const double2* __restrict__ vout, const int32_t*
       dd_accumulate(s, w[v] * x.x, w[v] * x.y);
     }
   }
-  perms[p] = make_double2(s.hr + s.lr, s.hi + s.li);
+  s = wave_reduce(s, plain != 0);
+  if (t == 0) perms[p] = make_double2(s.hr + s.lr, s.hi + s.li);
 }
 
 // Host description of the sweeps of a call.
@@ -479,8 +487,8 @@ static int boson_probs_grouped(hipStream_t st, const ph_c128* U, int64_t ldu, co
   rc = plan_ext_run(ns.data(), sw.vncols.data(), V, og, st, fill, C128(B_VOUT));
   if (rc) return rc;
   const unsigned pb = (unsigned)((npat + 255) / 256);
-  hipLaunchKernelGGL(k_boson_combine, dim3(pb), dim3(256), 0, st, C128(B_VOUT), (const int32_t*)nullptr, F64(P_W),
-                     I32(P_PV), npat, o.plain ? 1 : 0, C128(B_PERMS));
+  hipLaunchKernelGGL(k_boson_combine, dim3((unsigned)npat), dim3(64), 0, st, C128(B_VOUT), (const int32_t*)nullptr,
+                     F64(P_W), I32(P_PV), npat, o.plain ? 1 : 0, C128(B_PERMS));
   hipLaunchKernelGGL(k_boson_normalize, dim3(pb), dim3(256), 0, st, C128(B_PERMS), I32(P_IN), I32(P_PAT), n, npat,
                      (const double*)nullptr, probs, (double2*)nullptr);
   const hipError_t e = hipGetLastError();
@@ -729,8 +737,8 @@ static int boson_grad_grouped(hipStream_t st, const ph_c128* U, int32_t m, int64
     first += cnt;
   }
   const unsigned pb = (unsigned)((npat + 255) / 256);
-  hipLaunchKernelGGL(k_boson_combine, dim3(pb), dim3(256), 0, st, C128(B_POUT), I32(P_VPOS), F64(P_W), I32(P_PV),
-                     npat, o.plain ? 1 : 0, C128(B_PERMS));
+  hipLaunchKernelGGL(k_boson_combine, dim3((unsigned)npat), dim3(64), 0, st, C128(B_POUT), I32(P_VPOS), F64(P_W),
+                     I32(P_PV), npat, o.plain ? 1 : 0, C128(B_PERMS));
   hipLaunchKernelGGL(k_boson_normalize, dim3(pb), dim3(256), 0, st, C128(B_PERMS), I32(P_IN), I32(P_PAT), n, npat,
                      weights, probs, C128(B_GPERM));
   if (E > 0)
