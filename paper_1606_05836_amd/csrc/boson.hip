@@ -549,44 +549,54 @@ struct EntryDesc {
   int32_t pat, kind, idx, mode;
 };
 
-// D[e][k] = sum over the sweeps v of entry e's pattern, in order, of
-// w_v * (coefficient) * cm_v[k][column] for the columns of v that hold the
-// entry's mode (cm_v: the n x ncols column derivatives of sweep v).
-__global__ void k_boson_class_grad(const double2* __restrict__ cm, const int64_t* __restrict__ moff,
-                                   const int32_t* __restrict__ vncols, const int32_t* __restrict__ vcol,
-                                   const int32_t* __restrict__ colmodes, const int32_t* __restrict__ vcoef,
-                                   const double* __restrict__ coefs, const double* __restrict__ w,
-                                   const int32_t* __restrict__ pv, const EntryDesc* __restrict__ ent, int64_t nent,
-                                   int n, double2* __restrict__ D) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= nent * n) return;
-  const int64_t e = t / n;
-  const int k = (int)(t % n);
-  const EntryDesc d = ent[e];
-  double sr = 0.0, si = 0.0;
-  for (int32_t v = pv[d.pat]; v < pv[d.pat + 1]; ++v) {
-    const int nc = vncols[v];
-    const double2* c = cm + moff[v] + (int64_t)k * nc;
-    if (d.kind == ENT_SINGLE) {
-      const double2 x = c[d.idx];
-      sr = fma(w[v], x.x, sr);
-      si = fma(w[v], x.y, si);
-    } else if (d.kind == ENT_COLLIDED) {
-      const double cf = w[v] * coefs[vcoef[v] + d.idx];
-      const double2 x = c[0];
-      sr = fma(cf, x.x, sr);
-      si = fma(cf, x.y, si);
-    } else {
-      const int32_t* cmd = colmodes + vcol[v];
-      for (int j = 0; j < nc; ++j)
-        if (cmd[j] == d.mode) {
-          const double2 x = c[j];
-          sr = fma(w[v], x.x, sr);
-          si = fma(w[v], x.y, si);
-        }
+// D[e][k] = sum over the sweeps v of entry e's pattern of w_v *
+// (coefficient) * cm_v[k][column] for the columns of v that hold the entry's
+// mode (cm_v: the n x ncols column derivatives of sweep v).  One wavefront
+// per (e, k): lane t sums a contiguous slice of the sweeps in order, then the
+// lanes meet in a fixed butterfly, so the result depends only on the inputs.
+// The grid strides over the (e, k) pairs.
+__global__ __launch_bounds__(64) void k_boson_class_grad(
+    const double2* __restrict__ cm, const int64_t* __restrict__ moff, const int32_t* __restrict__ vncols,
+    const int32_t* __restrict__ vcol, const int32_t* __restrict__ colmodes, const int32_t* __restrict__ vcoef,
+    const double* __restrict__ coefs, const double* __restrict__ w, const int32_t* __restrict__ pv,
+    const EntryDesc* __restrict__ ent, int64_t nent, int n, double2* __restrict__ D) {
+  const int lane = threadIdx.x;
+  for (int64_t t = blockIdx.x; t < nent * n; t += gridDim.x) {
+    const int64_t e = t / n;
+    const int k = (int)(t % n);
+    const EntryDesc d = ent[e];
+    const int64_t v0 = pv[d.pat], cnt = pv[d.pat + 1] - v0;
+    const int64_t b0 = v0 + cnt * lane / 64, b1 = v0 + cnt * (lane + 1) / 64;
+    double sr = 0.0, si = 0.0;
+    for (int64_t v = b0; v < b1; ++v) {
+      const int nc = vncols[v];
+      const double2* c = cm + moff[v] + (int64_t)k * nc;
+      if (d.kind == ENT_SINGLE) {
+        const double2 x = c[d.idx];
+        sr = fma(w[v], x.x, sr);
+        si = fma(w[v], x.y, si);
+      } else if (d.kind == ENT_COLLIDED) {
+        const double cf = w[v] * coefs[vcoef[v] + d.idx];
+        const double2 x = c[0];
+        sr = fma(cf, x.x, sr);
+        si = fma(cf, x.y, si);
+      } else {
+        const int32_t* cmd = colmodes + vcol[v];
+        for (int j = 0; j < nc; ++j)
+          if (cmd[j] == d.mode) {
+            const double2 x = c[j];
+            sr = fma(w[v], x.x, sr);
+            si = fma(w[v], x.y, si);
+          }
+      }
     }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      sr += __shfl_xor(sr, off, 64);
+      si += __shfl_xor(si, off, 64);
+    }
+    if (lane == 0) D[t] = make_double2(sr, si);
   }
-  D[t] = make_double2(sr, si);
 }
 
 // dU[r][k] = sum over the entries of output mode r, in order, of g_p D[e][k]
@@ -742,7 +752,8 @@ static int boson_grad_grouped(hipStream_t st, const ph_c128* U, int32_t m, int64
   hipLaunchKernelGGL(k_boson_normalize, dim3(pb), dim3(256), 0, st, C128(B_PERMS), I32(P_IN), I32(P_PAT), n, npat,
                      weights, probs, C128(B_GPERM));
   if (E > 0)
-    hipLaunchKernelGGL(k_boson_class_grad, dim3((unsigned)((E * n + 255) / 256)), dim3(256), 0, st, C128(B_CM),
+    hipLaunchKernelGGL(k_boson_class_grad, dim3((unsigned)std::min<int64_t>(E * n, (int64_t)1 << 20)), dim3(64), 0,
+                       st, C128(B_CM),
                        reinterpret_cast<const int64_t*>(d + off[P_MOFF]), I32(P_VNCOLS), I32(P_VCOL), I32(P_COLM),
                        I32(P_VCOEF), F64(P_COEFS), F64(P_W), I32(P_PV),
                        reinterpret_cast<const EntryDesc*>(d + off[P_ENT]), E, n, C128(B_D));
