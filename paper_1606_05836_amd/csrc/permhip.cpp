@@ -198,10 +198,13 @@ namespace ph {
 // workgroups, as many as can be resident (or as waves per SIMD asks), at most
 // one per four super-chunks.
 int single_geometry(int n, const Opts& o, int cus, uint64_t nchunks, SweepGeom* g) {
-  const uint64_t nsuper = (nchunks + 63) / 64;
-  g->kern = single_kernel(n, o.algo);
+  // super-chunks of 64 chunks (one lane per term), or of 32 for the small
+  // sweeps that take two lanes per term
+  const bool pair = small_pair(n, nchunks);
+  const uint64_t nsuper = pair ? (nchunks + 31) / 32 : (nchunks + 63) / 64;
+  g->kern = pair ? small_pair_kernel(n, o.algo) : single_kernel(n, o.algo);
   if (!g->kern) return fail(PH_ERANGE, "no kernel for n=%d", n);
-  g->lds = single_lds_bytes(n);
+  g->lds = single_lds_bytes(n, pair || n >= 45);
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, g->kern, 256, g->lds);
   if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");

@@ -13,8 +13,20 @@ constexpr int NMAX_GRAD = 32;  // largest n of the backward sweep
 inline size_t table_elems(int n) { return (size_t)n * n; }
 // LDS of the one-matrix sweep: the table, with its column stride padded to an
 // even row count where two lanes share a term (n >= 45)
-inline size_t single_lds_bytes(int n) {
-  return (size_t)n * (n >= 45 ? 2 * ((n + 1) / 2) : n) * 16;
+// Small one-matrix sweeps take two lanes per term although one lane would
+// fit: with at most 2^15 chunks, one lane per chunk leaves SIMDs without a
+// wavefront, and two lanes halve each lane's serial chain (sweep_small.hip).
+// With more chunks one lane per term fills the chip and is faster.
+constexpr int SMALL_PAIR_NMIN = 12, SMALL_PAIR_NMAX = 21;
+constexpr uint64_t SMALL_PAIR_MAX_CHUNKS = (uint64_t)1 << 15;
+inline bool small_pair(int n, uint64_t nchunks) {
+  return n >= SMALL_PAIR_NMIN && n <= SMALL_PAIR_NMAX && nchunks <= SMALL_PAIR_MAX_CHUNKS;
+}
+
+// LDS table of the one-matrix sweep: n columns of n rows, or of 2 ceil(n/2)
+// rows when two lanes share a term
+inline size_t single_lds_bytes(int n, bool pair) {
+  return (size_t)n * (pair ? 2 * ((n + 1) / 2) : n) * 16;
 }
 
 // Per-matrix descriptor used by the batched kernels (device memory).
@@ -41,6 +53,7 @@ struct WorkItem {
 
 // size-range kernel lookups (sweep_single.hip compiled once per range)
 const void* single_kernel(int n, int algo);
+const void* small_pair_kernel(int n, int algo);  // SMALL_PAIR_NMIN <= n <= SMALL_PAIR_NMAX
 // batched persistent kernels (sweep_batched.hip), one per size bucket
 constexpr int NBUCKETS = 6;
 constexpr int BUCKET_LO[NBUCKETS] = {1, 17, 25, 33, 41, 45};
