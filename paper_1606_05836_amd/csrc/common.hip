@@ -23,13 +23,13 @@ __global__ void k_reset(uint32_t* __restrict__ counters, int count) {
   if (i < count) counters[i] = 0;
 }
 
-// Fixed-order reduction of partials [begin, end) by one block of a power-of-
-// two number of threads (at most 256): thread t sums a contiguous slice in
-// index order, then the slice totals are added in a fixed tree (slice t takes
-// slice t + s for s = nt/2, nt/4, ..., 1), so the result depends only on the
+// Fixed-order reduction of partials [begin, end) by one block of 64, 128 or
+// 256 threads: thread t sums a contiguous slice in index order, each wavefront
+// adds its lanes' sums in a fixed butterfly (no barrier), and the wavefront
+// totals are added in wavefront order, so the result depends only on the
 // partials and the block size.  The total is returned to every thread.
 __device__ dd2 reduce_range(const double4* __restrict__ p, int64_t begin, int64_t end, int plain) {
-  __shared__ dd2 part[256];
+  __shared__ dd2 wsum[4];
   const int t = threadIdx.x, nt = blockDim.x;
   const int64_t cnt = end - begin;
   const int64_t b0 = begin + cnt * t / nt, b1 = begin + cnt * (t + 1) / nt;
@@ -43,20 +43,19 @@ __device__ dd2 reduce_range(const double4* __restrict__ p, int64_t begin, int64_
       acc = dd_add(acc, dd2{v.x, v.y, v.z, v.w});
     }
   }
-  part[t] = acc;
+  acc = wave_reduce(acc, plain != 0);
+  if ((t & 63) == 0) wsum[t >> 6] = acc;  // lane 0's total
   __syncthreads();
-  for (int s = nt / 2; s > 0; s >>= 1) {
-    if (t < s) {
-      if (plain) {
-        part[t].hr += part[t + s].hr;
-        part[t].hi += part[t + s].hi;
-      } else {
-        part[t] = dd_add(part[t], part[t + s]);
-      }
+  dd2 s = wsum[0];
+  for (int w = 1; w < (nt >> 6); ++w) {
+    if (plain) {
+      s.hr += wsum[w].hr;
+      s.hi += wsum[w].hi;
+    } else {
+      s = dd_add(s, wsum[w]);
     }
-    __syncthreads();
   }
-  return part[0];
+  return s;
 }
 
 // The reduced sum, then the formula's scale: 2^-(n-1) (BB/FG, exact on both
