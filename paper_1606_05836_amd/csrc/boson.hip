@@ -343,7 +343,7 @@ struct Sweeps {
 // at least 4 Gray bits), sweeps per pattern, sweeps per call.
 constexpr int GROUP_MIN_SINGLES = 5;
 constexpr int64_t GROUP_MAX_PER_PATTERN = 4096;
-constexpr int64_t GROUP_MAX_SWEEPS = (int64_t)1 << 17;
+constexpr int64_t GROUP_MAX_SWEEPS = (int64_t)1 << 18;
 
 // min_singles: the fewest single-photon modes (columns of a grouped sweep)
 // a pattern needs to be grouped.

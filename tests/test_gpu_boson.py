@@ -236,10 +236,12 @@ def test_full_workload_forward_paths_agree(ph, full_workload):
 
 def test_full_workload_against_stored_exact(ph, full_workload):
     # exact Per of three of the 256 thirty-photon patterns, written by the
-    # oracle (tests/golden/make_golden.py boson): pattern 11 (3888
-    # multiplicity-grouped sweeps of 14 single-photon columns), 234 (one sweep
-    # over all 30 columns: the call's grouped-sweep budget is spent by then)
-    # and 5 (3 grouped sweeps of 28 columns); Eq. (1) normalises by prod t_j!
+    # oracle (tests/golden/make_golden.py boson): patterns 11 and 234 (3888
+    # multiplicity-grouped sweeps of 14 single-photon columns each, the most
+    # any pattern of the workload takes) and 5 (3 grouped sweeps of 28
+    # columns); Eq. (1) normalises by prod t_j!.  The probability call, the
+    # gradient call's by-product and the whole 2^29-term sweep of the gathered
+    # 30 x 30 matrix (perm_batched) are each held to the exact value.
     from fractions import Fraction
 
     u, ins, pats, w, pf, pg, du = full_workload
@@ -253,7 +255,8 @@ def test_full_workload_against_stored_exact(ph, full_workload):
         ex_re, ex_im = G.value_for("boson", name, a)
         d = O.occupation_factorials(ins) * O.occupation_factorials(pats[p])
         exact = (ex_re * ex_re + ex_im * ex_im) / d
-        for got in (pf[p], pg[p]):
+        whole = complex(ph.perm_batched(cuda(a[None])).cpu()[0])
+        for got in (pf[p], pg[p], abs(whole) ** 2 / float(d)):
             assert abs(Fraction(float(got)) - exact) <= Fraction(PROB_TOL) * exact, (p, got, float(exact))
         checked += 1
     assert checked == 3, "stored exact values of the thirty-photon patterns are missing"
