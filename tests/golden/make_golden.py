@@ -83,11 +83,10 @@ def minors_jobs():
 
 def boson_jobs():
     """U_{S,T} of three patterns of the 900-mode, 30-photon, 256-pattern
-    workload (main text, Eq. (1)); the library sweeps pattern 11 as 3888
-    multiplicity-grouped sweeps of 14 single-photon columns (the most any
-    grouped pattern takes), pattern 234 as one sweep over all 30 columns (the
-    call's sweep budget is spent by then), pattern 5 as 3 grouped sweeps of 28
-    columns.  Per is stored; the probability is |Per|^2 / prod t_j!."""
+    workload (main text, Eq. (1)): patterns 11 and 234 (each 3888
+    multiplicity-grouped sweeps of 14 single-photon columns in the library,
+    the most any pattern takes) and 5 (3 grouped sweeps of 28 columns).  Per
+    is stored; the probability is |Per|^2 / prod t_j!."""
     u, ins, pats = I.boson_workload()
     for p in (11, 234, 5):
         yield f"boson_workload_p{p}", O.gather_u_st(u, ins, pats[p])
