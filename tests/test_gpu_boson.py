@@ -343,3 +343,32 @@ def test_full_du_folds_photons_onto_columns(ph, m, ins, pat_seed):
         want[:, ins[k]] += du[:, k]
     assert np.array_equal(full, want)
     assert not np.any(full[:, [j for j in range(m) if j not in ins]])
+
+
+def test_grouped_sweep_budget_runs_out(ph):
+    # 70 thirty-photon patterns of 6 triply occupied and 12 single modes: each
+    # needs 4^6 = 4096 grouped sweeps, so the call's budget of 2^18 grouped
+    # sweeps lasts for the first 64 and the last 6 are swept whole.  The mixed
+    # call agrees with the all-whole (ungrouped) call, for the probabilities
+    # and the gradient.
+    m, n = 200, 30
+    u = I.haar(m, 61)
+    ins = list(range(n))
+    rng = np.random.default_rng(62)
+    pats = []
+    for _ in range(70):
+        modes = rng.choice(m, 18, replace=False)
+        pats.append(np.sort(np.concatenate([np.repeat(modes[:6], 3), modes[6:]])))
+    pats = np.array(pats, dtype=np.int64)
+    ud = cuda(u)
+    pf = ph.boson_probs(ud, ins, pats).cpu().numpy()
+    pu = ph.boson_probs(ud, ins, pats, ungrouped=True).cpu().numpy()
+    assert np.all(pf > 0)
+    assert np.max(np.abs(pf - pu) / pu) <= 2 * PROB_TOL
+    w = cuda(np.random.default_rng(63).uniform(0.5, 1.5, len(pats)))
+    pg, du = ph.boson_probs_grad(ud, ins, pats, weights=w)
+    pgu, duu = ph.boson_probs_grad(ud, ins, pats, weights=w, ungrouped=True)
+    assert np.max(np.abs(pg.cpu().numpy() - pu) / pu) <= 2 * PROB_TOL
+    du, duu = du.cpu().numpy(), duu.cpu().numpy()
+    scale = np.max(np.abs(duu), axis=1, keepdims=True) + 1e-300
+    assert np.max(np.abs(du - duu) / scale) <= 1e-9
