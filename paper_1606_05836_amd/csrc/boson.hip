@@ -173,7 +173,7 @@ static int upload_at(hipStream_t st, void* base, const size_t* off, const Piece*
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
   }
   if (s.cap < bytes) {
-    if (s.host) hipHostFree(s.host);
+    if (s.host) (void)hipHostFree(s.host);  // the old staging buffer's last upload has completed
     s.host = nullptr;
     s.cap = 0;
     const size_t cap = std::max(bytes, (size_t)1 << 16);
@@ -753,9 +753,8 @@ static int boson_grad_grouped(hipStream_t st, const ph_c128* U, int32_t m, int64
                      weights, probs, C128(B_GPERM));
   if (E > 0)
     hipLaunchKernelGGL(k_boson_class_grad, dim3((unsigned)std::min<int64_t>(E * n, (int64_t)1 << 20)), dim3(64), 0,
-                       st, C128(B_CM),
-                       reinterpret_cast<const int64_t*>(d + off[P_MOFF]), I32(P_VNCOLS), I32(P_VCOL), I32(P_COLM),
-                       I32(P_VCOEF), F64(P_COEFS), F64(P_W), I32(P_PV),
+                       st, C128(B_CM), reinterpret_cast<const int64_t*>(d + off[P_MOFF]), I32(P_VNCOLS), I32(P_VCOL),
+                       I32(P_COLM), I32(P_VCOEF), F64(P_COEFS), F64(P_W), I32(P_PV),
                        reinterpret_cast<const EntryDesc*>(d + off[P_ENT]), E, n, C128(B_D));
   const int64_t tot = (int64_t)m * n;
   hipLaunchKernelGGL(k_boson_scatter_entries, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, C128(B_D),

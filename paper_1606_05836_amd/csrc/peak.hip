@@ -53,14 +53,19 @@ extern "C" int ph_fp64_peak(int64_t iters, double* gflops, double* sclk_mhz, voi
   double* sink = reinterpret_cast<double*>(buf);
   unsigned long long* clk = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(buf) + 64);
   const int blocks = cus * 8;
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
-  hipLaunchKernelGGL(k_fp64_fma, dim3(blocks), dim3(256), 0, st, sink, iters / 4 > 0 ? iters / 4 : 1, clk);
-  hipEventRecord(e0, st);
-  hipLaunchKernelGGL(k_fp64_fma, dim3(blocks), dim3(256), 0, st, sink, iters, clk);
-  hipEventRecord(e1, st);
-  hipError_t e = hipEventSynchronize(e1);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) {
+    // a short warm-up launch, then the timed one
+    hipLaunchKernelGGL(k_fp64_fma, dim3(blocks), dim3(256), 0, st, sink, iters / 4 > 0 ? iters / 4 : 1, clk);
+    e = hipEventRecord(e0, st);
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_fp64_fma, dim3(blocks), dim3(256), 0, st, sink, iters, clk);
+    e = hipEventRecord(e1, st);
+  }
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
   float ms = 0;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
   unsigned long long h[2] = {0, 0};
@@ -68,11 +73,11 @@ extern "C" int ph_fp64_peak(int64_t iters, double* gflops, double* sclk_mhz, voi
   int wall_khz = 0;
   if (e == hipSuccess) {
     int dev = 0;
-    hipGetDevice(&dev);
-    e = hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev);
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev);
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   if (e != hipSuccess) return hip_fail(e, "fp64 peak run");
   const double flops = 2.0 * 8 * 4 * (double)iters * 256.0 * blocks;
   *gflops = flops / (ms * 1e-3) / 1e9;

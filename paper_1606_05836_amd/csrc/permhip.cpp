@@ -100,7 +100,7 @@ int workspace_slot(hipStream_t st, size_t bytes, int slot, void** out, bool* fre
       // the old buffer may still be in use by queued work on this stream
       e = hipStreamSynchronize(st);
       if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-      hipFree(b.p);
+      (void)hipFree(b.p);  // nothing queued uses it any more
       b.p = nullptr;
       b.cap = 0;
     }

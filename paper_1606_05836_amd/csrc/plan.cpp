@@ -97,11 +97,12 @@ static void destroy_impl(PlanImpl* p) {
   if (!p) return;
   // each execution waited for the previous one, so the last stream's work
   // is the last to touch the plan's memory
-  if (p->launched) hipStreamSynchronize(p->last_stream);
-  if (p->done) hipEventDestroy(p->done);
-  if (p->exec) hipGraphExecDestroy(p->exec);
-  if (p->graph) hipGraphDestroy(p->graph);
-  if (p->dmem) hipFree(p->dmem);
+  // (teardown: an error here has nothing left to undo, so it is not reported)
+  if (p->launched) (void)hipStreamSynchronize(p->last_stream);
+  if (p->done) (void)hipEventDestroy(p->done);
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->dmem) (void)hipFree(p->dmem);
   delete p;
 }
 
@@ -241,15 +242,15 @@ static int tune_shape(int n, int algo, bool plain, hipStream_t st, Shape* out) {
   res = a + elems;
   launch_fill_synthetic(a, elems, st);
   std::vector<int32_t> ns(copies, n), cs(copies);
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = PH_OK;
+  if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
+    rc = hip_fail(e, "tuning events");
   Opts o;
   o.algo = algo;
   o.plain = plain;
   float best = 1e30f;
   Shape best_s{default_chunk(n, algo), 0};
-  int rc = PH_OK;
   for (int c = lo; c <= hi && rc == PH_OK; ++c) {
     for (int w = 1; w <= occ && rc == PH_OK; ++w) {
       std::fill(cs.begin(), cs.end(), c);
@@ -259,25 +260,31 @@ static int tune_shape(int n, int algo, bool plain, hipStream_t st, Shape* out) {
       if (rc) break;
       float ms = 1e30f;
       for (int rep = 0; rep < 2 && rc == PH_OK; ++rep) {
-        hipEventRecord(e0, st);
-        rc = plan_exec(p, a, res, st);
-        hipEventRecord(e1, st);
-        hipEventSynchronize(e1);
+        if ((e = hipEventRecord(e0, st)) != hipSuccess) {
+          rc = hip_fail(e, "tuning event");
+          break;
+        }
+        if ((rc = plan_exec(p, a, res, st))) break;
         float t = 0;
-        hipEventElapsedTime(&t, e0, e1);
+        if ((e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+            (e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) {
+          rc = hip_fail(e, "tuning timing");
+          break;
+        }
         if (rep == 1) ms = t;
       }
       destroy_impl(p);
-      if (ms < best) {
+      if (rc == PH_OK && ms < best) {
         best = ms;
         best_s = Shape{c, w == occ ? 0 : w};
       }
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  hipStreamSynchronize(st);
-  hipFree(a);
+  // (teardown of the tuning buffers: errors here are not reported over rc)
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(a);
   *out = best_s;
   return rc;
 }
@@ -286,9 +293,10 @@ static int tune_shape(int n, int algo, bool plain, hipStream_t st, Shape* out) {
 // new tuning run (saved to both).
 int tuned_shape(int n, int algo, bool plain, hipStream_t st, Shape* out) {
   int dev = 0;
-  hipGetDevice(&dev);
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   hipDeviceProp_t prop;
-  hipError_t e = hipGetDeviceProperties(&prop, dev);
+  e = hipGetDeviceProperties(&prop, dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
   TuneKey k{PH_BUILD_ID, prop.gcnArchName, prop.multiProcessorCount, n, algo, plain ? 1 : 0};
   {
@@ -415,8 +423,11 @@ static hipError_t build_graph(PlanImpl* p, const Opts& o, const std::vector<std:
 
 int plan_build(const int32_t* n_host, const int64_t* off_host, int64_t batch, const Opts& o, const int32_t* c_force,
                hipStream_t st, PlanImpl** out, const int32_t* ncols_host) {
+  int dev = 0;
+  const hipError_t ed = hipGetDevice(&dev);
+  if (ed != hipSuccess) return hip_fail(ed, "hipGetDevice");
   auto* p = new PlanImpl;
-  hipGetDevice(&p->dev);
+  p->dev = dev;
   p->algo = o.algo;
   p->plain = o.plain;
   p->opts = o;
@@ -675,7 +686,8 @@ extern "C" int ph_plan_execute(void* plan, const ph_c128* A_packed, ph_c128* out
   auto* p = static_cast<PlanImpl*>(plan);
   if (p->batch > 0 && (!A_packed || !out)) return fail(PH_EINVAL, "A_packed or out is NULL");
   int dev = 0;
-  hipGetDevice(&dev);
+  const hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   if (dev != p->dev) return fail(PH_EINVAL, "plan was created on device %d, current device is %d", p->dev, dev);
   return plan_exec(p, reinterpret_cast<const double2*>(A_packed), reinterpret_cast<double2*>(out),
                    (hipStream_t)stream);
@@ -728,7 +740,8 @@ extern "C" int ph_perm_batched(const ph_c128* A_packed, const int64_t* offsets_h
   if ((rc = check_batch_args(n_host, batch))) return rc;
   if (batch > 0 && (!A_packed || !out)) return fail(PH_EINVAL, "A_packed or out is NULL");
   CacheKey key;
-  hipGetDevice(&key.dev);
+  hipError_t e = hipGetDevice(&key.dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   key.st = (hipStream_t)stream;
   key.algo = o.algo;
   key.plain = o.plain;
@@ -770,7 +783,8 @@ namespace ph {
 int plan_ext_run(const int32_t* n_host, const int32_t* ncols_host, int64_t batch, const Opts& o, hipStream_t st,
                  const std::function<int(PlanImpl*)>& fill, double2* out) {
   CacheKey key;
-  hipGetDevice(&key.dev);
+  const hipError_t e = hipGetDevice(&key.dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   key.st = st;
   key.algo = o.algo;
   key.plain = o.plain;
