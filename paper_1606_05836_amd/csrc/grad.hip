@@ -654,8 +654,8 @@ int grad_sweep(const double2* tabs, int n, int ncols, int64_t batch, const doubl
   const void* kern = nchunks % ng == 0 ? lay.kern : lay.kern_act;
   const size_t lds = (size_t)ncols * rows * sizeof(double2);
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds);
-  if (e != hipSuccess) return hip_fail(e, "occupancy");
+  int rc = resident_per_cu(kern, lds, &per_cu);
+  if (rc) return rc;
   per_cu = std::max(1, per_cu);
   if (o.waves > 0) per_cu = std::min(per_cu, o.waves);
   const int64_t blocks_full = (int64_t)cus * per_cu;
@@ -667,8 +667,7 @@ int grad_sweep(const double2* tabs, int n, int ncols, int64_t batch, const doubl
   const size_t ghat_elems = (size_t)units * 4 * ncols * rows;
   const size_t off_c = (((ghat_elems * sizeof(double2)) + 255) & ~(size_t)255);
   void* ws = nullptr;
-  int rc = workspace(st, off_c + 256, &ws);
-  if (rc) return rc;
+  if ((rc = workspace(st, off_c + 256, &ws))) return rc;
   char* base = static_cast<char*>(ws);
   GradArgs ga;
   ga.tabs = tabs;
@@ -683,7 +682,7 @@ int grad_sweep(const double2* tabs, int n, int ncols, int64_t batch, const doubl
   hipLaunchKernelGGL(k_reset1, dim3(1), dim3(1), 0, st, ga.counter);
   const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(blocks_full, units));
   void* args[] = {&ga};
-  e = hipLaunchKernel(kern, dim3((unsigned)grid), dim3(256), args, lds, st);
+  hipError_t e = hipLaunchKernel(kern, dim3((unsigned)grid), dim3(256), args, lds, st);
   if (e != hipSuccess) return hip_fail(e, "grad sweep launch");
   hipLaunchKernelGGL(k_grad_finalize, dim3((unsigned)batch), dim3(256), 0, st, ga.ghat, tabs, n, ncols, rows,
                      (int)s_per, o.plain ? 1 : 0, gout, pout, grad);

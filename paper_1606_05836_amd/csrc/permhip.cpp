@@ -116,6 +116,31 @@ int workspace_slot(hipStream_t st, size_t bytes, int slot, void** out, bool* fre
 
 int workspace(hipStream_t st, size_t bytes, void** out) { return workspace_slot(st, bytes, WS_SWEEP, out); }
 
+// Workgroups of 256 threads with `lds` bytes of dynamic LDS that fit on one
+// CU, asked of the runtime once per (kernel, LDS size) and kept: the answer
+// follows from the kernel's registers and LDS on the one architecture the
+// library runs on, and the query costs a small call more host time than the
+// rest of its launch preparation.
+int resident_per_cu(const void* kern, size_t lds, int* per_cu) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, size_t>, int> known;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = known.find({kern, lds});
+    if (it != known.end()) {
+      *per_cu = it->second;
+      return PH_OK;
+    }
+  }
+  int v = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, kern, 256, lds);
+  if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+  std::lock_guard<std::mutex> lk(mu);
+  known[{kern, lds}] = v;
+  *per_cu = v;
+  return PH_OK;
+}
+
 // ------------------------------------------------------------------ options
 
 int read_opts(const ph_opts* o, Opts* r) {
@@ -206,8 +231,8 @@ int single_geometry(int n, const Opts& o, int cus, uint64_t nchunks, SweepGeom* 
   if (!g->kern) return fail(PH_ERANGE, "no kernel for n=%d", n);
   g->lds = single_lds_bytes(n, pair || n >= 45);
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, g->kern, 256, g->lds);
-  if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+  int rc = resident_per_cu(g->kern, g->lds, &per_cu);
+  if (rc) return rc;
   if (per_cu < 1) return fail(PH_EHIP, "kernel for n=%d cannot be resident", n);
   if (o.waves > 0) per_cu = std::min(per_cu, o.waves);
   uint64_t blocks = (uint64_t)cus * per_cu;

@@ -41,6 +41,8 @@ enum WsSlot {
 // fresh (nullable) tells whether the buffer was (re)allocated by this call
 int workspace_slot(hipStream_t st, size_t bytes, int slot, void** out, bool* fresh = nullptr);
 int num_cus();
+// resident 256-thread workgroups per CU of kern with lds bytes of dynamic LDS
+int resident_per_cu(const void* kern, size_t lds, int* per_cu);
 int gray_bits(int n, int algo);
 int min_chunk_log2(int nb);
 int pick_chunk_log2(int n, int algo, int requested);

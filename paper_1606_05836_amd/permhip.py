@@ -98,12 +98,40 @@ def opts(algo: str | int = "glynn", accum: str | int = "dd", chunk_log2: int = 0
     return PhOpts(int(a), int(c), int(chunk_log2), int(waves), int(flags))
 
 
-def _stream(t: torch.Tensor):
-    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+_OPTS: dict = {}
+
+
+def _opts_shared(algo="glynn", accum="dd", chunk_log2: int = 0, waves: int = 0, flags: int = 0) -> PhOpts:
+    """opts() for the calls below, built once per distinct argument tuple: the
+    library only reads the struct (a const ph_opts*), so one instance serves
+    every call with the same options and a small call skips building it."""
+    key = (algo, accum, chunk_log2, waves, flags)
+    o = _OPTS.get(key)
+    if o is None:
+        o = opts(algo, accum, chunk_log2, waves, flags)
+        if len(_OPTS) < 1024:
+            _OPTS[key] = o
+    return o
+
+
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
+def _stream_of(dev: torch.device) -> int:
+    """Handle of the current stream on `dev`, as an integer for a void*
+    argument (without building a torch.cuda.Stream object per call)."""
+    if _raw_stream is not None:
+        return _raw_stream(dev.index)
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def _stream(t: torch.Tensor) -> int:
+    return _stream_of(t.device)
 
 
 def _ptr(t: torch.Tensor | None):
-    return ctypes.c_void_p(t.data_ptr() if t is not None else 0)
+    """Device address for a void* argument (None passes NULL)."""
+    return t.data_ptr() if t is not None else None
 
 
 def _need_c128_cuda(name: str, t: torch.Tensor):
@@ -128,26 +156,31 @@ def perm(a: torch.Tensor, algo="glynn", accum="dd", chunk_log2: int = 0, waves: 
     a 0-dim complex128 tensor.  For a (..., n, n) tensor the permanents of all
     matrices go through ph_perm_batched and come back with shape (...)."""
     _need_c128_cuda("a", a)
-    if a.dim() < 2 or a.shape[-1] != a.shape[-2]:
+    shape = a.shape
+    if len(shape) < 2 or shape[-1] != shape[-2]:
         raise ValueError("a must be (..., n, n)")
-    if a.dim() > 2:
+    if len(shape) > 2:
         if out is not None:
             raise ValueError("out is supported for a single matrix only")
-        lead, n = a.shape[:-2], a.shape[-1]
+        lead, n = shape[:-2], shape[-1]
         flat = a.reshape(-1, n, n)
         res = perm_batched(flat, algo, accum, chunk_log2, waves) if flat.shape[0] else \
             torch.empty(0, dtype=torch.complex128, device=a.device)
         return res.reshape(lead)
-    n = a.shape[0]
-    if n > 0 and a.stride(1) != 1:
-        a = a.contiguous()
-    lda = a.stride(0) if n > 0 else 1
+    n = shape[0]
+    lda = 1
+    if n > 0:
+        lda, s1 = a.stride()
+        if s1 != 1:
+            a = a.contiguous()
+            lda = n
+    dev = a.device
     if out is None:
-        out = torch.empty((), dtype=torch.complex128, device=a.device)
+        out = torch.empty((), dtype=torch.complex128, device=dev)
     else:
-        _need_out("out", out, torch.complex128, 1, a.device)
-    o = opts(algo, accum, chunk_log2, waves)
-    check(lib().ph_perm(_ptr(a), n, lda, _ptr(out), ctypes.byref(o), _stream(a)))
+        _need_out("out", out, torch.complex128, 1, dev)
+    check(lib().ph_perm(a.data_ptr(), n, lda, out.data_ptr(), _opts_shared(algo, accum, chunk_log2, waves),
+                        _stream_of(dev)))
     return out
 
 
@@ -163,7 +196,7 @@ def perm_noalloc(a: torch.Tensor, out: torch.Tensor, algo="glynn", accum="dd", c
     n = a.shape[0]
     if n > 0 and a.stride(1) != 1:
         raise ValueError("a's rows must be contiguous (stride(1) == 1): no copy is made here")
-    o = opts(algo, accum, chunk_log2, waves)
+    o = _opts_shared(algo, accum, chunk_log2, waves)
     check(lib().ph_perm_noalloc(_ptr(a), n, a.stride(0) if n > 0 else 1, _ptr(out), ctypes.byref(o), _stream(a)))
     return out
 
@@ -183,7 +216,7 @@ def perm_ryser_paired(a: torch.Tensor, accum="dd", chunk_log2: int = 0,
         out = torch.empty((), dtype=torch.complex128, device=a.device)
     else:
         _need_out("out", out, torch.complex128, 1, a.device)
-    o = opts("ryser", accum, chunk_log2)
+    o = _opts_shared("ryser", accum, chunk_log2)
     check(lib().ph_perm_ryser_paired(_ptr(a), n, a.stride(0) if n > 0 else 1, _ptr(out), ctypes.byref(o),
                                      _stream(a)))
     return out
@@ -218,7 +251,7 @@ def perm_partial(a: torch.Tensor, k_begin: int, k_end: int, algo="glynn", accum=
         out = torch.empty(4, dtype=torch.float64, device=a.device)
     else:
         _need_out("out", out, torch.float64, 4, a.device)
-    o = opts(algo, accum, chunk_log2, waves)
+    o = _opts_shared(algo, accum, chunk_log2, waves)
     check(lib().ph_perm_partial(_ptr(a), n, a.stride(0) if n > 0 else 1, int(k_begin), int(k_end), _ptr(out),
                                 ctypes.byref(o), _stream(a)))
     return out

@@ -301,6 +301,26 @@ def test_binding_rejects_mismatched_buffers_before_the_call():
         P._need_out("out", torch.zeros(1, dtype=torch.float64), torch.complex128, 1, torch.device("cpu"))
 
 
+def test_shared_options_match_fresh_ones(L):
+    # the small-call paths reuse one options struct per distinct argument
+    # tuple; its fields must be those opts() builds, and the chunk-length
+    # query must read the same values through either
+    from paper_1606_05836_amd import permhip as P
+
+    fields = [f for f, _ in P.PhOpts._fields_]
+    for args in (("glynn", "dd", 0, 0), ("ryser", "plain", 7, 2), (P.PH_RYSER, P.PH_ACC_DD, 40, 0),
+                 ("glynn", "plain", 0, 0, P.PH_FLAG_UNGROUPED)):
+        a = P._opts_shared(*args)
+        assert a is P._opts_shared(*args)
+        b = P.opts(*args)
+        assert [getattr(a, f) for f in fields] == [getattr(b, f) for f in fields], args
+        ca, cb = ctypes.c_int32(0), ctypes.c_int32(0)
+        assert L.ph_perm_chunk_log2(44, a, ctypes.byref(ca)) == 0
+        assert L.ph_perm_chunk_log2(44, ctypes.byref(b), ctypes.byref(cb)) == 0
+        assert ca.value == cb.value, args
+    assert P._opts_shared("glynn", "dd") is not P._opts_shared("glynn", "plain")
+
+
 def test_missing_library_fails_loudly(monkeypatch):
     # no CPU fallback: without libpermhip.so the binding raises instead of
     # computing anything elsewhere
