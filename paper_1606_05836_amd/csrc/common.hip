@@ -34,13 +34,24 @@ __device__ dd2 reduce_range(const double4* __restrict__ p, int64_t begin, int64_
   const int64_t cnt = end - begin;
   const int64_t b0 = begin + cnt * t / nt, b1 = begin + cnt * (t + 1) / nt;
   dd2 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t q = b0; q < b1; ++q) {
-    const double4 v = p[q];
-    if (plain) {
-      acc.hr += v.x;
-      acc.hi += v.z;
-    } else {
-      acc = dd_add(acc, dd2{v.x, v.y, v.z, v.w});
+  // the loads of a group of U partials are all issued before the first add
+  // (one memory round trip per group, not per partial); the adds keep the
+  // order q = b0, b0 + 1, ...
+  constexpr int U = 4;
+  for (int64_t q0 = b0; q0 < b1; q0 += U) {
+    double4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (q0 + u < b1) v[u] = p[q0 + u];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (q0 + u >= b1) break;
+      if (plain) {
+        acc.hr += v[u].x;
+        acc.hi += v[u].z;
+      } else {
+        acc = dd_add(acc, dd2{v[u].x, v[u].y, v[u].z, v[u].w});
+      }
     }
   }
   acc = wave_reduce(acc, plain != 0);

@@ -526,19 +526,38 @@ __global__ void k_grad_finalize(const double2* __restrict__ ghat, const double2*
                                 int ncols, int rows, int s_per, int plain, const double2* __restrict__ gout,
                                 double2* __restrict__ pout, double2* __restrict__ grad) {
   __shared__ dd2 row0[NMAX_GRAD];
+  __shared__ double2 a0s[NMAX_GRAD];  // row 0 of the matrix, for the Laplace expansion
   const int64_t mat = blockIdx.x;
   const int64_t slots = (int64_t)s_per * 4, first = mat * slots;
   const double2 g = gout ? gout[mat] : make_double2(1.0, 0.0);
+  if (pout) {
+    const double2* t = tabs + (size_t)mat * ncols * rows;
+    for (int j = threadIdx.x; j < ncols; j += blockDim.x) {
+      double2 a0 = t[(size_t)j * rows];
+      if (j >= 1) a0 = make_double2(-0.5 * a0.x, -0.5 * a0.y);  // exact
+      a0s[j] = a0;
+    }
+  }
   for (int e = threadIdx.x; e < n * ncols; e += blockDim.x) {
     const int i = e / ncols, j = e % ncols;
     dd2 s = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t q = 0; q < slots; ++q) {
-      const double2 v = ghat[(first + q) * ncols * rows + (size_t)j * rows + i];
-      if (plain) {
-        s.hr += v.x;
-        s.hi += v.y;
-      } else {
-        dd_accumulate(s, v.x, v.y);
+    // the loads of U slots are issued before the first add (one memory round
+    // trip per group); the adds keep the slot order
+    constexpr int U = 8;
+    for (int64_t q0 = 0; q0 < slots; q0 += U) {
+      double2 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (q0 + u < slots) v[u] = ghat[(first + q0 + u) * ncols * rows + (size_t)j * rows + i];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (q0 + u >= slots) break;
+        if (plain) {
+          s.hr += v[u].x;
+          s.hi += v[u].y;
+        } else {
+          dd_accumulate(s, v[u].x, v[u].y);
+        }
       }
     }
     if (i == 0) row0[j] = s;
@@ -550,11 +569,9 @@ __global__ void k_grad_finalize(const double2* __restrict__ ghat, const double2*
   if (pout) {
     __syncthreads();
     if (threadIdx.x == 0) {
-      const double2* t = tabs + (size_t)mat * ncols * rows;
       dd2 acc = {0.0, 0.0, 0.0, 0.0};
       for (int j = 0; j < ncols; ++j) {
-        double2 a0 = t[(size_t)j * rows];
-        if (j >= 1) a0 = make_double2(-0.5 * a0.x, -0.5 * a0.y);  // exact
+        const double2 a0 = a0s[j];
         const dd2 m = row0[j];
         if (plain) {
           acc.hr += a0.x * m.hr - a0.y * m.hi;

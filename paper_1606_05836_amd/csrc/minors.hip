@@ -184,9 +184,19 @@ __global__ void k_minors_finalize(const double4* __restrict__ partials, int n_ro
   const int mat = blockIdx.x, l = threadIdx.x, nc = n_rows + 1;
   if (l >= nc) return;
   dd2 t = {0.0, 0.0, 0.0, 0.0};
-  for (int b = 0; b < bpm; ++b) {
-    const double4 v = partials[((int64_t)mat * bpm + b) * nc + l];
-    t = dd_add(t, dd2{v.x, v.y, v.z, v.w});
+  // the loads of U partials are issued before the first add (one memory
+  // round trip per group); the adds keep the block order
+  constexpr int U = 8;
+  for (int b0 = 0; b0 < bpm; b0 += U) {
+    double4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (b0 + u < bpm) v[u] = partials[((int64_t)mat * bpm + b0 + u) * nc + l];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (b0 + u >= bpm) break;
+      t = dd_add(t, dd2{v[u].x, v[u].y, v[u].z, v[u].w});
+    }
   }
   out[(int64_t)mat * nc + l] =
       make_double2(ldexp(t.hr, -n_rows) + ldexp(t.lr, -n_rows), ldexp(t.hi, -n_rows) + ldexp(t.li, -n_rows));
