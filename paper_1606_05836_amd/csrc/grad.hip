@@ -530,7 +530,11 @@ __global__ void k_grad_finalize(const double2* __restrict__ ghat, const double2*
   const int64_t mat = blockIdx.x;
   const int64_t slots = (int64_t)s_per * 4, first = mat * slots;
   const double2 g = gout ? gout[mat] : make_double2(1.0, 0.0);
-  if (pout) {
+  // entries e = i ncols + j are spread over the gridDim.y workgroups of the
+  // matrix; the first holds every entry of row 0 (e < ncols <= blockDim.x)
+  // and adds the Laplace expansion along it
+  const bool first_wg = blockIdx.y == 0;
+  if (pout && first_wg) {
     const double2* t = tabs + (size_t)mat * ncols * rows;
     for (int j = threadIdx.x; j < ncols; j += blockDim.x) {
       double2 a0 = t[(size_t)j * rows];
@@ -538,7 +542,7 @@ __global__ void k_grad_finalize(const double2* __restrict__ ghat, const double2*
       a0s[j] = a0;
     }
   }
-  for (int e = threadIdx.x; e < n * ncols; e += blockDim.x) {
+  for (int e = blockIdx.y * blockDim.x + threadIdx.x; e < n * ncols; e += blockDim.x * gridDim.y) {
     const int i = e / ncols, j = e % ncols;
     dd2 s = {0.0, 0.0, 0.0, 0.0};
     // the loads of U slots are issued before the first add (one memory round
@@ -566,7 +570,7 @@ __global__ void k_grad_finalize(const double2* __restrict__ ghat, const double2*
     // g * conj(M)
     grad[mat * n * ncols + e] = make_double2(g.x * mr + g.y * mi, g.y * mr - g.x * mi);
   }
-  if (pout) {
+  if (pout && first_wg) {
     __syncthreads();
     if (threadIdx.x == 0) {
       dd2 acc = {0.0, 0.0, 0.0, 0.0};
@@ -701,7 +705,9 @@ int grad_sweep(const double2* tabs, int n, int ncols, int64_t batch, const doubl
   void* args[] = {&ga};
   hipError_t e = hipLaunchKernel(kern, dim3((unsigned)grid), dim3(256), args, lds, st);
   if (e != hipSuccess) return hip_fail(e, "grad sweep launch");
-  hipLaunchKernelGGL(k_grad_finalize, dim3((unsigned)batch), dim3(256), 0, st, ga.ghat, tabs, n, ncols, rows,
+  // one workgroup per 256 entries of a matrix's n x ncols gradient
+  const unsigned fin_y = (unsigned)((n * ncols + 255) / 256);
+  hipLaunchKernelGGL(k_grad_finalize, dim3((unsigned)batch, fin_y), dim3(256), 0, st, ga.ghat, tabs, n, ncols, rows,
                      (int)s_per, o.plain ? 1 : 0, gout, pout, grad);
   e = hipGetLastError();
   return e == hipSuccess ? PH_OK : hip_fail(e, "grad launch");
