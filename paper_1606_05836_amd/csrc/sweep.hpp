@@ -120,10 +120,11 @@ __device__ __forceinline__ void fma_lds(double2 (&r)[N], double s, const double2
 
 // sb += (+-) prod_i r_i.  K independent product chains (rows k, k+K, ...) give
 // instruction-level parallelism; the last complex multiply is fused into the
-// accumulation (4 FMAs).
+// accumulation (4 FMAs).  n = 44 takes three chains: the fourth chain's
+// registers hold the staged update column of the one-matrix sweep.
 template <int N>
 __device__ __forceinline__ void term(const double2 (&r)[N], double2& sb, bool neg) {
-  constexpr int K = N < 4 ? N : 4;
+  constexpr int K = N < 4 ? N : (N == 44 ? 3 : 4);
   double2 ch[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) ch[k] = r[k];
@@ -214,10 +215,41 @@ struct Resident {
   }
 };
 
+// Update column b in the lane-distributed layout of Resident::col, read from
+// the LDS table.  A staged sweep fills one such buffer several steps before
+// the step that flips bit b, so that step is a DPP update like a resident
+// column's instead of a wave-uniform LDS read per row at the step itself.
+template <int N, int ALGO, int NP>
+__device__ __forceinline__ void stage_column(double (&x)[NP], const double2* T, int b) {
+  using S = Shape<N, ALGO>;
+  static_assert(NP == S::NP, "staged column of the resident layout");
+  const int l16 = threadIdx.x & 15;
+  const double* c = reinterpret_cast<const double*>(T + (b + S::OFF) * N);
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    // an in-range read on every lane (no branch in the sweep); lanes past the
+    // column's 2N doubles are never broadcast by add_resident
+    const int d = p * 16 + l16;
+    x[p] = c[d < 2 * N ? d : 2 * N - 1];
+  }
+}
+
+// The next step offset s' > s of an unrolled block of 2^LOGU steps whose
+// flipped bit ctz(s') is not resident (>= DR); 0 if there is none.
+template <int LOGU, int DR>
+constexpr int next_staged(int s) {
+  for (int t = s + 1; t < (1 << LOGU); ++t)
+    if (__builtin_ctz(t) >= DR) return t;
+  return 0;
+}
+
 // One lane sweeps the chunk [k0, k0 + 2^c) and folds it into acc.
 // Requires LOGU <= c <= nb (c == 0 only when the formula has a single term);
 // nb follows from the table's ncols columns (N for a square matrix).
-template <int N, int ALGO, int DR>
+// STAGE: the steps that flip a non-resident bit (and the block boundaries)
+// take their column from one staged buffer (stage_column), refilled right
+// after each use with the next such step's column.
+template <int N, int ALGO, int DR, bool STAGE = false>
 __device__ __forceinline__ void sweep_chunk(uint64_t k0, int c, const Resident<N, ALGO, DR>& res, const double2* T,
                                             dd2& acc, bool plain, bool active, int ncols = N) {
   using S = Shape<N, ALGO>;
@@ -232,6 +264,11 @@ __device__ __forceinline__ void sweep_chunk(uint64_t k0, int c, const Resident<N
   } else {
     const double one = 1.0, mone = -1.0;
     const uint32_t nblk = 1u << (c - LOGU);
+    constexpr int S1 = next_staged<LOGU, DR>(0);  // first staged step of a block
+    double xs[S::NP];
+    if constexpr (STAGE) {
+      stage_column<N, ALGO>(xs, T, S1 != 0 ? __builtin_ctz(S1) : LOGU);
+    }
     for (uint32_t m = 0; m < nblk; ++m) {
       const uint32_t tb = m << LOGU;
       static_for<1, U>([&](auto sc) {
@@ -246,10 +283,18 @@ __device__ __forceinline__ void sweep_chunk(uint64_t k0, int c, const Resident<N
           const uint64_t k = k0 + tb + s;
           sg = ((k >> (b + 1)) & 1) ? mone : one;
         }
-        if constexpr (b < DR)
+        if constexpr (b < DR) {
           add_resident<N, S::NP>(r, res.col[b], sg);
-        else
+        } else if constexpr (STAGE) {
+          add_resident<N, S::NP>(r, xs, sg);
+          constexpr int sn = next_staged<LOGU, DR>(s);
+          if constexpr (sn != 0)
+            stage_column<N, ALGO>(xs, T, __builtin_ctz(sn));
+          else  // this block's boundary column (an unused in-range one after the last block)
+            stage_column<N, ALGO>(xs, T, m + 1 < nblk ? LOGU + __builtin_ctz(m + 1) : LOGU);
+        } else {
           fma_lds<N>(r, sg, T + (b + S::OFF) * N);
+        }
         term<N>(r, sb, (s & 1) != 0);
         // keep steps apart: overlapping the next update with this product
         // would need two copies of the row sums in registers
@@ -259,7 +304,16 @@ __device__ __forceinline__ void sweep_chunk(uint64_t k0, int c, const Resident<N
         // block boundary: offset t = (m+1) U flips bit LOGU + ctz(m+1)
         const int b = LOGU + __builtin_ctz(m + 1);
         const uint64_t k = k0 + tb + U;
-        fma_lds<N>(r, ((k >> (b + 1)) & 1) ? -1.0 : 1.0, T + (b + S::OFF) * N);
+        const double sgb = ((k >> (b + 1)) & 1) ? -1.0 : 1.0;
+        if constexpr (STAGE) {
+          add_resident<N, S::NP>(r, xs, sgb);
+          if constexpr (S1 != 0)
+            stage_column<N, ALGO>(xs, T, __builtin_ctz(S1));
+          else
+            stage_column<N, ALGO>(xs, T, m + 2 < nblk ? LOGU + __builtin_ctz(m + 2) : LOGU);
+        } else {
+          fma_lds<N>(r, sgb, T + (b + S::OFF) * N);
+        }
         term<N>(r, sb, false);
       }
       flush(acc, sb, plain, active);
