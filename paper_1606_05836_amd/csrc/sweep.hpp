@@ -265,9 +265,15 @@ __device__ __forceinline__ void sweep_chunk(uint64_t k0, int c, const Resident<N
     const double one = 1.0, mone = -1.0;
     const uint32_t nblk = 1u << (c - LOGU);
     constexpr int S1 = next_staged<LOGU, DR>(0);  // first staged step of a block
+    // a staged load with no step left to use it reads table column 0 (present
+    // in every table, even one of fewer columns than rows)
+    constexpr int UNUSED = -S::OFF;
     double xs[S::NP];
     if constexpr (STAGE) {
-      stage_column<N, ALGO>(xs, T, S1 != 0 ? __builtin_ctz(S1) : LOGU);
+      if constexpr (S1 != 0)
+        stage_column<N, ALGO>(xs, T, __builtin_ctz(S1));
+      else
+        stage_column<N, ALGO>(xs, T, nblk > 1 ? LOGU : UNUSED);
     }
     for (uint32_t m = 0; m < nblk; ++m) {
       const uint32_t tb = m << LOGU;
@@ -290,8 +296,8 @@ __device__ __forceinline__ void sweep_chunk(uint64_t k0, int c, const Resident<N
           constexpr int sn = next_staged<LOGU, DR>(s);
           if constexpr (sn != 0)
             stage_column<N, ALGO>(xs, T, __builtin_ctz(sn));
-          else  // this block's boundary column (an unused in-range one after the last block)
-            stage_column<N, ALGO>(xs, T, m + 1 < nblk ? LOGU + __builtin_ctz(m + 1) : LOGU);
+          else  // this block's boundary column
+            stage_column<N, ALGO>(xs, T, m + 1 < nblk ? LOGU + __builtin_ctz(m + 1) : UNUSED);
         } else {
           fma_lds<N>(r, sg, T + (b + S::OFF) * N);
         }
@@ -310,7 +316,7 @@ __device__ __forceinline__ void sweep_chunk(uint64_t k0, int c, const Resident<N
           if constexpr (S1 != 0)
             stage_column<N, ALGO>(xs, T, __builtin_ctz(S1));
           else
-            stage_column<N, ALGO>(xs, T, m + 2 < nblk ? LOGU + __builtin_ctz(m + 2) : LOGU);
+            stage_column<N, ALGO>(xs, T, m + 2 < nblk ? LOGU + __builtin_ctz(m + 2) : UNUSED);
         } else {
           fma_lds<N>(r, sgb, T + (b + S::OFF) * N);
         }

@@ -33,12 +33,15 @@ __device__ __forceinline__ void run_item(const double2* lds, int c, int ncols, c
   // the item loop keeps extra state live: above n = 32 at most 3 resident
   // columns, above n = BATCHED_DPP_NMAX every column comes from LDS
   constexpr int DR = N > BATCHED_DPP_NMAX ? 0 : (N > 32 && S::D > 3 ? 3 : S::D);
+  // n = 17..32: the block boundaries read a staged column (above n = 32 the
+  // staged column does not fit next to the item loop's state)
+  constexpr bool STG = N >= 17 && N <= 32;
   Resident<N, ALGO, DR> res;
   res.load(lds);
   dd2 acc = {0.0, 0.0, 0.0, 0.0};
   for (int r = wave; r < w.rounds; r += 4) {
     const uint64_t chunk = ((uint64_t)(w.super0 + r) << 6) + lane;
-    sweep_chunk<N, ALGO>(chunk << c, c, res, lds, acc, plain != 0, chunk < nchunks, ncols);
+    sweep_chunk<N, ALGO, DR, STG>(chunk << c, c, res, lds, acc, plain != 0, chunk < nchunks, ncols);
   }
   acc = wave_reduce(acc, plain != 0);
   if (lane == 0) partials[slot * 4 + wave] = make_double4(acc.hr, acc.lr, acc.hi, acc.li);

@@ -66,6 +66,22 @@ struct ResidentPair {
   }
 };
 
+// This lane's half of update column b in the ResidentPair layout, read from
+// the LDS table (stage_column's counterpart): an in-range read on every lane;
+// lanes past the half's 2R doubles are never broadcast.
+template <int N, int ALGO, int NP>
+__device__ __forceinline__ void stage_column_pair(double (&x)[NP], const double2* Tl, int b) {
+  using P = PairShape<N, ALGO>;
+  static_assert(NP == P::NP, "staged column of the resident layout");
+  const int l16 = threadIdx.x & 15;
+  const double* c = reinterpret_cast<const double*>(Tl + (b + P::OFF) * P::RS);
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int d = p * 16 + l16;
+    x[p] = c[d < 2 * P::R ? d : 2 * P::R - 1];
+  }
+}
+
 // Row sums of this lane's half at the Gray word of k0 (as seed()).
 template <int N, int ALGO, int R>
 __device__ __forceinline__ void seed_pair(double2 (&r)[R], uint64_t k0, const double2* Tl, bool upper) {
@@ -132,8 +148,10 @@ __device__ __forceinline__ void term_pair(const double2 (&r)[R], double2& sb, do
 }
 
 // The pair of lanes sweeps the chunk [k0, k0 + 2^c); `active` folds it into
-// acc (true on the lower lane of an in-range chunk only).
-template <int N, int ALGO>
+// acc (true on the lower lane of an in-range chunk only).  STAGE: each block
+// boundary's column comes from a staged buffer filled right after the
+// previous boundary (every other step's column is resident).
+template <int N, int ALGO, bool STAGE = false>
 __device__ __forceinline__ void sweep_chunk_pair(uint64_t k0, int c, const ResidentPair<N, ALGO>& res,
                                                  const double2* Tl, bool upper, dd2& acc, bool plain, bool active) {
   using P = PairShape<N, ALGO>;
@@ -144,6 +162,11 @@ __device__ __forceinline__ void sweep_chunk_pair(uint64_t k0, int c, const Resid
   double2 sb = make_double2(0.0, 0.0), up = make_double2(0.0, 0.0);
   const double one = 1.0, mone = -1.0;
   const uint32_t nblk = 1u << (c - LOGU);
+  static_assert(!STAGE || P::D == LOGU, "staging covers the block boundaries only");
+  double xs[P::NP];
+  // block 0's boundary flips bit LOGU; with no boundary in the chunk the load
+  // reads table column 0 and goes unused
+  if constexpr (STAGE) stage_column_pair<N, ALGO>(xs, Tl, nblk > 1 ? LOGU : -P::OFF);
   term_pair<R>(r, sb, up, (k0 & 1) != 0);  // offset 0
   for (uint32_t m = 0; m < nblk; ++m) {
     const uint32_t tb = m << LOGU;
@@ -167,7 +190,14 @@ __device__ __forceinline__ void sweep_chunk_pair(uint64_t k0, int c, const Resid
     if (m + 1 < nblk) {
       const int b = LOGU + __builtin_ctz(m + 1);
       const uint64_t k = k0 + tb + U;
-      fma_lds<R>(r, ((k >> (b + 1)) & 1) ? -1.0 : 1.0, Tl + (b + P::OFF) * P::RS);
+      const double sgb = ((k >> (b + 1)) & 1) ? -1.0 : 1.0;
+      if constexpr (STAGE) {
+        add_resident<R, P::NP>(r, xs, sgb);
+        // the next block's boundary column (column 0, unused, after the last)
+        stage_column_pair<N, ALGO>(xs, Tl, m + 2 < nblk ? LOGU + __builtin_ctz(m + 2) : -P::OFF);
+      } else {
+        fma_lds<R>(r, sgb, Tl + (b + P::OFF) * P::RS);
+      }
       term_pair<R>(r, sb, up, false);
     }
     flush(acc, sb, plain, active);

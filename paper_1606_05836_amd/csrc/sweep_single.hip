@@ -44,8 +44,8 @@ __global__ __launch_bounds__(256) void k_sweep_single(const double2* __restrict_
     res.load(Tl);
     for (uint64_t s = s0; s < s1; ++s) {
       const uint64_t chunk = (s << 5) + (lane & 31);
-      sweep_chunk_pair<N, ALGO>((chunk0 + chunk) << c, c, res, Tl, upper, acc, plain != 0,
-                                chunk < nchunks && !upper);
+      sweep_chunk_pair<N, ALGO, true>((chunk0 + chunk) << c, c, res, Tl, upper, acc, plain != 0,
+                                      chunk < nchunks && !upper);
     }
   } else {
     const uint64_t nsuper = (nchunks + 63) >> 6;

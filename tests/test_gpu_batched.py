@@ -66,10 +66,14 @@ def test_plan_replay_with_new_pointers_and_offsets(ph):
     r2 = plan(packed(m2), out=out).cpu().numpy()
     r1b = plan(packed(m1)).cpu().numpy()
     assert np.array_equal(r1, r1b)  # deterministic replay
+    # two summation orders: the plan's chunk length (picked by timing) and the
+    # single call's 16-term chunks on two lanes per term.  Each is held to
+    # 1e-12 of the exact value in this file, so they lie within 2e-12 of each
+    # other (measured 2e-15 to 1.8e-13 depending on the tuned length)
     for mats, res in ((m1, r1), (m2, r2)):
         for m, g in zip(mats, res):
             single = complex(ph.perm(torch.from_numpy(m).to("cuda")).cpu())
-            assert abs(complex(g) - single) <= 1e-13 * abs(single)
+            assert abs(complex(g) - single) <= 2e-12 * abs(single)
     # explicit offsets: the same matrices stored in reverse order with gaps
     order = list(reversed(range(len(ns))))
     flat, offs, at = [], [0] * len(ns), 0
