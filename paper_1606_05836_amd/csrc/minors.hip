@@ -67,7 +67,12 @@ template <int N>
 __global__ __launch_bounds__(256) void k_minors(const double2* __restrict__ tabs, int bpm, uint64_t nchunks,
                                                 double4* __restrict__ partials) {
   using S = Shape<N, ALGO_GLYNN>;
-  constexpr int NC = N + 1, C = MINORS_C, DR = S::D;
+  // STG (N = 14..30): bits 0..2 resident, bit 3 and the block boundaries read
+  // a staged column (stage_column) refilled after each use; the other orders
+  // keep bits 0..3 resident and read the boundary column from LDS at the step
+  // (the staged column would cost N = 12, 13 a wave per SIMD and spill at 31)
+  constexpr bool STG = N >= 14 && N <= 30;
+  constexpr int NC = N + 1, C = MINORS_C, DR = STG ? S::D - 1 : S::D;
   static_assert(S::LOGU == 4 && N >= C, "block and chunk sizes");
   __shared__ double2 T[N * NC];
   __shared__ dd2 wsum[4][NC];
@@ -94,7 +99,10 @@ __global__ __launch_bounds__(256) void k_minors(const double2* __restrict__ tabs
     for (int q = 0; q < 4; ++q) low[q] = make_double2(0.0, 0.0);
 #pragma unroll
     for (int q = 0; q < C - 4; ++q) blkc[q] = make_double2(0.0, 0.0);
-    for (uint32_t m = 0; m < (1u << (C - 4)); ++m) {
+    constexpr uint32_t NBLK = 1u << (C - 4);
+    double xs[S::NP];
+    if constexpr (STG) stage_column<N, ALGO_GLYNN>(xs, T, 3);  // block 0's bit-3 step
+    for (uint32_t m = 0; m < NBLK; ++m) {
       // delta of Gray bit 3 inside block m: bit 3 of t ^ bit 0 of m
       const double d3 = (m & 1) ? mone : one;
       double2 bs = make_double2(0.0, 0.0);
@@ -105,16 +113,28 @@ __global__ __launch_bounds__(256) void k_minors(const double2* __restrict__ tabs
           double sg;
           if constexpr (b + 1 < 4) sg = (((s >> (b + 1)) & 1) == 0) ? one : mone;
           else sg = (m & 1) ? mone : one;  // bit 4 of t = bit 0 of m
-          if constexpr (b < DR)
+          static_assert(b < DR || b == 3, "bits above DR other than 3 are block boundaries");
+          if constexpr (b < DR) {
             add_resident<N, S::NP>(r, res.col[b], sg);
-          else
+          } else if constexpr (!STG) {
             fma_lds<N>(r, sg, T + (b + 1) * N);
+          } else {
+            add_resident<N, S::NP>(r, xs, sg);
+            // the next block's boundary column (column 0, unused, after the last)
+            stage_column<N, ALGO_GLYNN>(xs, T, m + 1 < NBLK ? 4 + __builtin_ctz(m + 1) : -1);
+          }
         } else {
           if (m > 0) {
             // block boundary: t = 16 m flips Gray bit 4 + ctz(m)
             const int b = 4 + __builtin_ctz(m);
             const uint64_t k = k0 + ((uint64_t)m << 4);
-            fma_lds<N>(r, ((k >> (b + 1)) & 1) ? -1.0 : 1.0, T + (b + 1) * N);
+            const double sgb = ((k >> (b + 1)) & 1) ? -1.0 : 1.0;
+            if constexpr (STG) {
+              add_resident<N, S::NP>(r, xs, sgb);
+              stage_column<N, ALGO_GLYNN>(xs, T, 3);  // this block's bit-3 step
+            } else {
+              fma_lds<N>(r, sgb, T + (b + 1) * N);
+            }
           }
         }
         double2 v = row_product<N>(r);

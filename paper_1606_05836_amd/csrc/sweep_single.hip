@@ -52,11 +52,15 @@ __global__ __launch_bounds__(256) void k_sweep_single(const double2* __restrict_
     const uint64_t s0 = nsuper * wave / nwaves;
     const uint64_t s1 = nsuper * (wave + 1) / nwaves;
     stage_table<N, ALGO>(lds_tab, a, lda);
-    // n = 33..44: one resident column fewer, its registers holding the
-    // staged column that every other non-resident step reads (no LDS read
-    // per row at those steps: n = 40 2.0%, n = 42 and 44 6.3-6.6% faster)
-    constexpr bool STG = N >= 33 && N <= 44 && Shape<N, ALGO>::D >= 1;
-    Resident<N, ALGO, STG ? Shape<N, ALGO>::D - 1 : Shape<N, ALGO>::D> res;
+    // The steps whose update column is not resident read a staged column
+    // instead of one LDS entry per row at the step.  n = 24..32 (two waves
+    // per SIMD already) stage the block boundaries in spare registers;
+    // n = 33..44 keep one resident column fewer and its registers hold the
+    // staged one (n = 40 2.0%, n = 42 and 44 6.3-6.6% faster).  n <= 23 would
+    // lose a wave per SIMD to the extra registers.
+    constexpr int DF = Shape<N, ALGO>::D;
+    constexpr bool STG = N >= 24 && N <= 44 && DF >= 1;
+    Resident<N, ALGO, (STG && N >= 33) ? DF - 1 : DF> res;
     res.load(lds_tab);
     for (uint64_t s = s0; s < s1; ++s) {
       const uint64_t chunk = (s << 6) + lane;
