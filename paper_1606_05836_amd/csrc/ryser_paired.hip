@@ -191,11 +191,18 @@ __global__ __launch_bounds__(256) void k_ryser_paired_2l(const double2* __restri
   const uint64_t pid = (uint64_t)blockIdx.x * (blockDim.x >> 1) + (threadIdx.x >> 6) * 32 + (lane & 31);
   const uint32_t nblk = 1u << (c - LOGU);
   const double one = 1.0, mone = -1.0;
+  // n >= 23 (two waves per SIMD already): each block boundary's column comes
+  // from a staged buffer refilled after the previous boundary (column 0,
+  // unused, when no boundary is left); below, the extra registers would cost
+  // a wave per SIMD and the boundary reads its column from LDS at the step
+  constexpr bool STG = N >= 23;
+  double xs[P::NP];
   dd2 acc = {0.0, 0.0, 0.0, 0.0};
   for (uint64_t ch = pid; ch < nchunks; ch += pairs) {
     const uint64_t k0 = ch << c;
     double2 r[R];
     seed_pair<N, ALGO_RYSER>(r, k0, Tl, upper);
+    if constexpr (STG) stage_column_pair<N, ALGO_RYSER>(xs, Tl, nblk > 1 ? LOGU : 0);
     double2 sb = make_double2(0.0, 0.0), up_p = make_double2(0.0, 0.0), up_q = make_double2(0.0, 0.0);
     term_paired<R>(r, tr, sb, up_p, up_q, false, sgn_c);  // index k0 (even)
     for (uint32_t m = 0; m < nblk; ++m) {
@@ -222,7 +229,13 @@ __global__ __launch_bounds__(256) void k_ryser_paired_2l(const double2* __restri
         // block boundary: index k0 + tb + U flips bit LOGU + ctz(m + 1)
         const int b = LOGU + __builtin_ctz(m + 1);
         const uint64_t k = k0 + tb + U;
-        fma_lds<R>(r, ((k >> (b + 1)) & 1) ? -1.0 : 1.0, Tl + b * RS);
+        const double sgb = ((k >> (b + 1)) & 1) ? -1.0 : 1.0;
+        if constexpr (STG) {
+          add_resident<R, P::NP>(r, xs, sgb);
+          stage_column_pair<N, ALGO_RYSER>(xs, Tl, m + 2 < nblk ? LOGU + __builtin_ctz(m + 2) : 0);
+        } else {
+          fma_lds<R>(r, sgb, Tl + b * RS);
+        }
         term_paired<R>(r, tr, sb, up_p, up_q, false, sgn_c);
       }
       flush(acc, sb, plain != 0, !upper);
