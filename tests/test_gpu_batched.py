@@ -111,6 +111,27 @@ def test_mixed_batch_against_stored_exact(ph):
     assert np.median(rel) <= 1e-9
 
 
+@pytest.mark.parametrize("c", [4, 5])
+def test_short_chunks_against_stored_exact(ph, c):
+    """Plans of chunks of one and two 16-step blocks, where the sweeps' staged
+    update column (the block boundaries) is loaded and goes unused or serves
+    one boundary: the stored exact values of the benchmark batch (n = 16..26)
+    within the same 1e-10."""
+    ns, mats = I.mixed_batch_16_26()
+    gold = G.load("batch")
+    if not gold:
+        pytest.skip("no stored batch values")
+    stored = sorted(int(name.rsplit("_b", 1)[1]) for name in gold)
+    picks = [b for b in stored if ns[b] >= 18][:14] + [b for b in stored if ns[b] == 17][:2]
+    assert len(picks) >= 12
+    sub = [mats[b] for b in picks]
+    got = ph.Plan([ns[b] for b in picks], chunk_log2=c)(packed(sub)).cpu().numpy()
+    for i, b in enumerate(picks):
+        n, sha, v = gold[next(k for k in gold if int(k.rsplit("_b", 1)[1]) == b)]
+        assert I.sha256_of(mats[b]) == sha and ns[b] == n
+        assert O.rel_err(complex(got[i]), v) <= 1e-10, (b, n, c)
+
+
 def test_fp64_peak_microbenchmark(ph):
     gflops, mhz = ph.fp64_peak(1 << 12)
     assert gflops > 10_000  # far below the 78.6 TFLOP/s spec; a sanity floor

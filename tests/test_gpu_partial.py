@@ -194,7 +194,13 @@ def test_segmented_run_resumes_to_the_same_bits(ph, tmp_path):
     ("ryser", 41, 6), ("ryser", 44, 6),
     # two lanes per term from n = 45 (rows split in halves, odd n padded)
     ("glynn", 45, 6), ("glynn", 48, 6), ("glynn", 52, 6), ("ryser", 45, 6),
-    ("ryser", 47, 6), ("ryser", 52, 6), ("glynn", 48, 0)])
+    ("ryser", 47, 6), ("ryser", 52, 6), ("glynn", 48, 0),
+    # chunks of one and two blocks of 16 steps for every layout with a staged
+    # update column: no block boundary in the chunk (the staged load goes
+    # unused) and one boundary (staged, then the unused load after it)
+    ("glynn", 26, 4), ("ryser", 30, 5), ("glynn", 36, 4), ("glynn", 36, 5), ("ryser", 38, 5),
+    ("glynn", 42, 4), ("glynn", 43, 5), ("ryser", 44, 5), ("glynn", 47, 4), ("glynn", 47, 5),
+    ("ryser", 50, 5)])
 def test_large_n_haar_ranges_against_oracle(ph, algo, n, c):
     # the Haar blocks of the n = 40 / 44 workload recipe (and the same recipe
     # at the other orders): short ranges high in the index space, and the last
