@@ -32,7 +32,10 @@
 // steps, live in VGPRs laid out for 64-bit DPP row broadcast (row_newbcast);
 // each row-sum update is one v_fmac_f64 whose first operand is the broadcast
 // column entry and whose second is +-1.0 (the same rounding as an add).  The
-// remaining steps read their column from LDS (all lanes the same address).
+// remaining steps read their column from a staged buffer in the same layout,
+// refilled from the LDS table ahead of them (stage_column), or, in sweeps
+// without registers to spare, from LDS at the step (all lanes the same
+// address).
 // The new value of the flipped bit is "set" iff bit ctz(t)+1 of k is clear;
 // that bit comes from t except at t = L/2, where it is the chunk parity and
 // differs between neighbouring lanes.
