@@ -102,7 +102,7 @@ enum {
 /* Per(A) of one n x n matrix into *out (one complex128, device).
  * A: device, row stride lda >= n (elements).  0 <= n <= PH_NMAX.
  * The 2^(n-1) (Glynn) or 2^n (Ryser) terms are cut into contiguous Gray-code
- * chunks, one per GPU lane at a time (one per pair of lanes from n = 45, and
+ * chunks, one per GPU lane at a time (one per pair of lanes from n = 49, and
  * for n = 12..21 when there are at most 2^15 chunks, too few to give every
  * SIMD a wavefront); see the formulas above. */
 int ph_perm(const ph_c128* A, int32_t n, int64_t lda, ph_c128* out, const ph_opts* opt, void* stream);

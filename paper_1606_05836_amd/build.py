@@ -123,9 +123,10 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
         # there when the bucket starts at or below BATCHED_DPP_NMAX
         if "batched" in kernel:
             return int(m.group(1)) <= BATCHED_DPP_NMAX
-        # one-matrix sweeps: one lane per term up to DPP_NMAX, two lanes per
-        # term from PAIR_NMIN on (csrc/sweep_pair.hpp); both keep resident
-        # columns
+        # one-matrix sweeps: one lane per term up to n = 48 (resident columns
+        # up to DPP_NMAX, a staged column in the same layout from n = 24),
+        # two lanes per term from PAIR_NMIN on (csrc/ph_internal.hpp); all
+        # read update columns with DPP
         return True
 
     # kernels that read resident columns with DPP: no spill code of any kind

@@ -229,7 +229,7 @@ int single_geometry(int n, const Opts& o, int cus, uint64_t nchunks, SweepGeom* 
   const uint64_t nsuper = pair ? (nchunks + 31) / 32 : (nchunks + 63) / 64;
   g->kern = pair ? small_pair_kernel(n, o.algo) : single_kernel(n, o.algo);
   if (!g->kern) return fail(PH_ERANGE, "no kernel for n=%d", n);
-  g->lds = single_lds_bytes(n, pair || n >= 45);
+  g->lds = single_lds_bytes(n, pair || n >= PAIR_NMIN);
   int per_cu = 0;
   int rc = resident_per_cu(g->kern, g->lds, &per_cu);
   if (rc) return rc;

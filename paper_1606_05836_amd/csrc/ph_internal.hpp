@@ -11,8 +11,12 @@ constexpr int NMAX_GRAD = 32;  // largest n of the backward sweep
 // Complex entries of the per-matrix table (n columns of n entries; a table
 // with ncols < n columns uses the first ncols * n of them).
 inline size_t table_elems(int n) { return (size_t)n * n; }
-// LDS of the one-matrix sweep: the table, with its column stride padded to an
-// even row count where two lanes share a term (n >= 45)
+// The one-matrix sweep takes two lanes per term from n = PAIR_NMIN on: below,
+// the n row sums fit one lane's registers next to the update columns (at
+// n = 45..48 a single staged column, every step reading it; sweep_single.hip),
+// and one lane per term issues fewer instructions (no cross-lane product).
+constexpr int PAIR_NMIN = 49;
+
 // Small one-matrix sweeps take two lanes per term although one lane would
 // fit: with at most 2^15 chunks, one lane per chunk leaves SIMDs without a
 // wavefront, and two lanes halve each lane's serial chain (sweep_small.hip).

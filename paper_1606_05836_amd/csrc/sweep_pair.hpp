@@ -1,5 +1,6 @@
 // Two lanes per term, for the orders whose n row sums no longer fit one
-// lane's registers next to the resident update columns (n >= PAIR_NMIN).
+// lane's registers next to the update columns (the one-matrix sweep from
+// n = PAIR_NMIN on), and for small sweeps that need more lanes than chunks.
 //
 // Lane l and lane l + 32 of a wavefront walk the same chunk.  The lower lane
 // owns rows 0..R-1 and the upper lane rows R..2R-1, R = ceil(n/2); for odd n
@@ -16,11 +17,10 @@
 // N..2R-1 padded: a_{pad,0} = 1 (BB/FG), every other padded entry 0.  The
 // Ryser seed sets the padded row sum to 1 itself.
 #pragma once
+#include "ph_internal.hpp"
 #include "sweep.hpp"
 
 namespace ph {
-
-constexpr int PAIR_NMIN = 45;
 
 template <int N, int ALGO>
 struct PairShape {

@@ -56,10 +56,12 @@ __global__ __launch_bounds__(256) void k_sweep_single(const double2* __restrict_
     // instead of one LDS entry per row at the step.  n = 24..32 (two waves
     // per SIMD already) stage the block boundaries in spare registers;
     // n = 33..44 keep one resident column fewer and its registers hold the
-    // staged one (n = 40 2.0%, n = 42 and 44 6.3-6.6% faster).  n <= 23 would
-    // lose a wave per SIMD to the extra registers.
+    // staged one (n = 40 2.0%, n = 42 and 44 6.3-6.6% faster); n = 45..48
+    // keep none, every step reading the staged column (5-7% faster than two
+    // lanes per term).  n <= 23 would lose a wave per SIMD to the extra
+    // registers.
     constexpr int DF = Shape<N, ALGO>::D;
-    constexpr bool STG = N >= 24 && N <= 44 && DF >= 1;
+    constexpr bool STG = N >= 24 && (DF >= 1 || N > DPP_NMAX);
     Resident<N, ALGO, (STG && N >= 33) ? DF - 1 : DF> res;
     res.load(lds_tab);
     for (uint64_t s = s0; s < s1; ++s) {

@@ -172,10 +172,10 @@ def test_larger_size_buckets_exact(ph):
 
 
 @pytest.mark.timeout(900)
-def test_batch_with_a_large_order_takes_the_two_lane_sweep(ph):
-    # a full n = 45 permanent: about 2.5 minutes
-    # orders >= 45 in a batch are swept one by one after the plan's graph (two
-    # lanes per term); the small ones stay in the graph
+def test_batch_with_a_large_order_takes_the_one_matrix_sweep(ph):
+    # a full n = 45 permanent: about 2.3 minutes
+    # orders >= 45 in a batch are swept one by one after the plan's graph by
+    # the one-matrix kernel; the small ones stay in the graph
     mats = [I.diag_matrix(45, 1 + 1j), gauss_int(6, 1), I.haar1600_block(20)]
     got = ph.perm_batched([torch.from_numpy(m).to("cuda") for m in mats]).cpu().numpy()
     assert complex(got[0]) == complex(-4194304, -4194304)

@@ -192,9 +192,10 @@ def test_segmented_run_resumes_to_the_same_bits(ph, tmp_path):
     ("glynn", 33, 6), ("glynn", 40, 6), ("glynn", 40, 0), ("glynn", 41, 6), ("glynn", 42, 6),
     ("glynn", 43, 6), ("glynn", 44, 6), ("glynn", 44, 0), ("ryser", 33, 6), ("ryser", 40, 6),
     ("ryser", 41, 6), ("ryser", 44, 6),
-    # two lanes per term from n = 45 (rows split in halves, odd n padded)
+    # one lane per term with every step's column staged at n = 45..48, two
+    # lanes per term from n = 49 (rows split in halves, odd n padded)
     ("glynn", 45, 6), ("glynn", 48, 6), ("glynn", 52, 6), ("ryser", 45, 6),
-    ("ryser", 47, 6), ("ryser", 52, 6), ("glynn", 48, 0),
+    ("ryser", 47, 6), ("ryser", 52, 6), ("glynn", 48, 0), ("glynn", 49, 6), ("glynn", 50, 0),
     # chunks of one and two blocks of 16 steps for every layout with a staged
     # update column: no block boundary in the chunk (the staged load goes
     # unused) and one boundary (staged, then the unused load after it)
@@ -225,9 +226,10 @@ def test_large_n_haar_ranges_against_oracle(ph, algo, n, c):
             assert abs(v - e) <= 1e-12 * abs(e), (kb, ke, v, e)
 
 
-@pytest.mark.parametrize("n", [45, 47])
+@pytest.mark.parametrize("n", [45, 47, 49, 51])
 def test_odd_large_n_shares_exact_on_diag_one_plus_i(ph, n):
-    # odd orders pad the upper half with a row whose sum stays 1
+    # odd orders: one lane per term up to 47; from 49 two lanes share a term
+    # and the upper half is padded with a row whose sum stays 1
     a = cuda(I.diag_matrix(n, 1 + 1j))
     m = 1 << 30
     kb = (1 << (n - 3)) + (7 << 30)
@@ -284,12 +286,12 @@ def test_command_line_runs_and_resumes(ph, tmp_path):
     assert abs(per - whole) <= 1e-15 * abs(whole)
 
 
-@pytest.mark.parametrize("n", [1, 5, 16, 33, 44, 45, 52])
+@pytest.mark.parametrize("n", [1, 5, 16, 33, 44, 45, 49, 52])
 @pytest.mark.parametrize("algo", ["glynn", "ryser"])
 def test_strided_rows_match_contiguous(ph, n, algo):
     # every workgroup builds its table from A through lda: a view with row and
     # column offsets inside a 64 x 64 parent (lda = 64) must give the bits of
-    # its contiguous copy, on the one-lane (n <= 44) and two-lane (n >= 45) sweeps
+    # its contiguous copy, on the one-lane (n <= 48) and two-lane (n >= 49) sweeps
     u = cuda(I.haar(64, 7))
     view = u[3:3 + n, 5:5 + n]
     assert view.stride(0) == 64
@@ -318,13 +320,13 @@ def test_longest_chunk_exact(ph, algo):
     assert got == want
 
 
-def test_longest_chunk_two_lanes_exact(ph):
-    # the two-lane sweep (n >= 45) at the longest chunk: two chunks of 2^24
-    # terms of diag(1+i), n = 46, high in the index space; every term is
-    # (1+i)^46 = 2^23 i^23
-    n = 46
+@pytest.mark.parametrize("n", [46, 50])
+def test_longest_chunk_large_n_exact(ph, n):
+    # the longest chunk on the one-lane sweep with every column staged
+    # (n = 46) and on the two-lane sweep (n = 50): two chunks of 2^24 terms of
+    # diag(1+i), high in the index space; every term is (1+i)^n = 2^(n/2) i^(n/2)
     a = cuda(I.diag_matrix(n, 1 + 1j))
     L = 1 << 24
     kb = (1 << (n - 2)) + 5 * L
     p = ph.perm_partial(a, kb, kb + 2 * L, chunk_log2=24).cpu().tolist()
-    assert complex(p[0] + p[1], p[2] + p[3]) == 2 * L * 2 ** 23 * 1j ** 23
+    assert complex(p[0] + p[1], p[2] + p[3]) == 2 * L * 2 ** (n // 2) * 1j ** (n // 2)
